@@ -1,0 +1,231 @@
+/*
+ * xy.h - C ABI of the MI355X (gfx950) hot path for Monte Carlo simulation of
+ * the classical three-dimensional XY model, after Lan, Hsieh and Kao,
+ * "High-precision Monte Carlo study of the three-dimensional XY model on GPU"
+ * (arXiv:1211.0780).
+ *
+ * The library keeps every configuration of every lattice resident in device
+ * memory (Sec. II: all spin configurations at all temperatures stay in GPU
+ * memory and all updates run on the GPU) and exposes four verbs:
+ *
+ *   xy_init      allocate / adopt device state, random or ordered start
+ *   xy_sweep     n_metro checkerboard Metropolis sweeps followed by n_or
+ *                over-relaxation sweeps of every configuration (Sec. II, the
+ *                Monte Carlo step; over-relaxation is Eq. (2))
+ *   xy_measure   per-configuration energy and magnetisation moments
+ *                (Eq. (1) energy, Eq. (4) magnetisation, inputs of Eq. (5))
+ *   xy_exchange  one parallel-tempering exchange step per lattice (Eq. (3))
+ *
+ * plus a graph-replayed driver loop (xy_run), state access for checkpointing
+ * and testing, and error reporting.  Nothing here takes or returns a PyTorch
+ * type: device buffers are plain pointers, streams are hipStream_t passed as
+ * void*.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Lattice l is a periodic L_l x L_l x L_l simple cubic lattice with
+ *    N_l = L_l^3 sites, site index i = x + L*(y + L*z).  J = k_B = 1 and
+ *    beta = 1/T.
+ *  - Lattice l carries R_l configurations, one per entry of its beta-ladder.
+ *    "beta-position" k (0 <= k < R_l) names the ladder entry beta_l[k];
+ *    ladders are strictly ascending.  Exchanges permute which stored
+ *    configuration sits at which beta-position; every call below that takes
+ *    or returns per-configuration data indexes it by (lattice, beta-position).
+ *  - The flat "position index" of (l, k) is sum_{l' < l} R_l' + k, and
+ *    R_total = sum_l R_l.
+ *  - Randomness is Philox4x32-10 with key (seed mod 2^32, seed >> 32) and
+ *    counter (c0, c1, (l << 16) | k, (phase << 24) | substep): c0 is the site
+ *    (or exchange pair) index, c1 the sweep counter t (or exchange counter
+ *    tau), phase 1 = initial state, 2 = Metropolis, 3 = exchange.  Uniforms
+ *    are U(r) = (r >> 8) * 2^-24.  Random draws depend only on these
+ *    counters, never on thread layout, so results do not depend on tiling.
+ *  - All device work is ordered on the context's stream.  Calls return
+ *    without waiting unless they hand data to host memory.
+ *  - No call throws; each returns an xy_status and, on failure, leaves a
+ *    message readable with xy_last_error(ctx).  Calls on one context are not
+ *    thread-safe; distinct contexts are independent.
+ */
+#ifndef XY_H
+#define XY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xy_ctx_s *xy_ctx;
+
+typedef enum {
+    XY_OK = 0,
+    XY_ERR_ARG = 1,         /* invalid argument (null pointer, range, ladder order, size) */
+    XY_ERR_ODD_L = 2,       /* L odd or L < 4: the checkerboard needs an even, bipartite lattice */
+    XY_ERR_OOM = 3,         /* device or host allocation failed */
+    XY_ERR_HIP = 4,         /* a HIP runtime call failed; the message names it */
+    XY_ERR_STATE = 5,       /* state blob or device state inconsistent (bad blob, NaN angle) */
+    XY_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+} xy_status;
+
+typedef enum {
+    XY_FP32 = 0, /* angles stored and updated in float32; reductions and the
+                    exchange in float64; Metropolis decisions near the
+                    threshold re-evaluated in float64 */
+    XY_FP64 = 1  /* angles stored and updated in float64 (plain kernels) */
+} xy_prec;
+
+typedef enum {
+    XY_START_RANDOM = 0,  /* theta = 2*pi*U(r0) with phase 1, c1 = 0, substep 0 */
+    XY_START_ORDERED = 1  /* theta = 0 everywhere */
+} xy_start;
+
+/* xy_config.flags */
+#define XY_F_NO_RECHECK  0x1u /* FP32: take Metropolis decisions in float32 only */
+#define XY_F_NO_AUTOTUNE 0x2u /* use the built-in tile choice instead of timing candidates */
+
+typedef struct {
+    int32_t n_lattices;          /* >= 1 */
+    const int32_t *L;            /* [n_lattices] linear sizes, even, 4 <= L <= 1024; copied */
+    const int32_t *n_replicas;   /* [n_lattices] ladder lengths, 1 <= R <= 65535; copied */
+    const double *beta;          /* [R_total] ladders concatenated by lattice, each strictly
+                                    ascending, finite, >= 0; copied */
+    uint64_t seed;               /* Philox key */
+    int32_t prec;                /* xy_prec */
+    int32_t start;               /* xy_start */
+    void *angles_dev;            /* optional caller-owned device buffer of xy_angles_bytes()
+                                    bytes (layout below), or NULL to let the library allocate.
+                                    A caller-owned buffer is never freed by the library and
+                                    must outlive the context. */
+    void *stream;                /* hipStream_t for all work, or NULL for the null stream */
+    uint32_t flags;              /* XY_F_* */
+} xy_config;
+
+/*
+ * Device layout of the angle buffer (what angles_dev must hold): for each
+ * lattice in order, for each storage slot r < R_l, for each colour c in
+ * {0, 1} (colour = (x + y + z) mod 2), the N_l/2 sites of that colour ordered
+ * (z, y, x/2) with x/2 fastest.  FP32 buffers hold angles in turns
+ * (theta / 2pi, in [0, 1)); FP64 buffers hold radians in [0, 2pi).  Storage
+ * slot and beta-position coincide at start and are permuted by exchanges;
+ * use xy_get_angles / xy_set_angles for position-indexed access.
+ */
+
+/* Bytes of angle storage a configuration needs (0 on invalid input). */
+size_t xy_angles_bytes(const xy_config *cfg);
+
+/*
+ * Create a context: validate cfg (XY_ERR_ODD_L for odd or small L,
+ * XY_ERR_ARG for the rest), allocate device state, write the start
+ * configuration, set t = tau = 0.  On success *out owns the context; on
+ * failure *out is NULL.
+ */
+xy_status xy_init(const xy_config *cfg, xy_ctx *out);
+
+/*
+ * One sweep of every configuration (Sec. II): n_metro Metropolis substeps,
+ * each a half-sweep over colour 0 then colour 1 with proposal
+ * theta' = 2*pi*U(r0) accepted iff U(r1) < exp(-beta*dE), then n_or
+ * over-relaxation substeps (Eq. (2)), each colour 0 then colour 1.  Then
+ * t <- t + 1.  n_metro, n_or >= 0 and n_metro + n_or >= 1.  Asynchronous.
+ */
+xy_status xy_sweep(xy_ctx ctx, int32_t n_metro, int32_t n_or);
+
+/*
+ * Observables of every configuration in its current state, by position
+ * index: obs[5*p + {0..4}] = {E, E/N, |m|, |m|^2, |m|^4} with
+ * E = -sum_<ij> cos(theta_i - theta_j) (Eq. (1)) and
+ * |m| = |sum_j (cos theta_j, sin theta_j)| / N (Eq. (4), one sample).
+ * Sums are accumulated in float64.  obs has 5*R_total doubles; if
+ * obs_on_device is nonzero it is a device pointer and the call is
+ * asynchronous, otherwise it is host memory and the call waits for it.
+ * Returns XY_ERR_STATE if any energy is not finite.
+ */
+xy_status xy_measure(xy_ctx ctx, double *obs, int32_t obs_on_device);
+
+/*
+ * One parallel-tempering exchange step on every lattice (Eq. (3)): pairs
+ * (k, k+1) with k = tau mod 2, tau mod 2 + 2, ... swap their configurations
+ * iff U(r0) < exp((beta_k - beta_k+1)(E_k - E_k+1)), r drawn with counter
+ * (k, tau, l << 16, 3 << 24).  E is the float64 energy of the current
+ * configurations (measured first if the state changed since the last
+ * measurement).  Swaps relabel storage slots; no angle moves.  Then
+ * tau <- tau + 1.  n_acc (nullable, host) receives R_total cumulative
+ * acceptance counts, entry p counting swaps of pair (p, p+1) within its
+ * lattice (the last entry of each lattice stays 0); the call then waits.
+ */
+xy_status xy_exchange(xy_ctx ctx, int64_t *n_acc);
+
+/*
+ * The production loop, captured once as a HIP graph and replayed: n_sweeps
+ * times { xy_sweep(n_metro, n_or); measure into obs_dev; exchange if
+ * (sweep index + 1) % exchange_every == 0 }.  exchange_every = 0 disables
+ * exchange.  obs_dev: device buffer of n_sweeps*5*R_total doubles, sweep s at
+ * offset 5*R_total*s, laid out as xy_measure; may be NULL to skip the copy
+ * (observables are still computed for the exchange).  Asynchronous.
+ */
+xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
+                 int32_t exchange_every, double *obs_dev);
+
+/*
+ * xy_sweep with every kernel launch bracketed by HIP events on the
+ * context's stream (profiling aid; same result as xy_sweep).  ms[0], ms[1]
+ * receive the summed device time of the Metropolis and over-relaxation
+ * half-sweep kernels, ms[2] of everything else the sweep launched;
+ * launches[0..2] the matching kernel counts.  Waits.
+ */
+xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *ms,
+                            int32_t *launches);
+
+/* Copy the N_l angles (radians in [0, 2pi), natural site order) of the
+ * configuration at (lattice, beta_pos) to host memory.  Waits. */
+xy_status xy_get_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *host);
+
+/* Overwrite that configuration from host radians (any finite values; they are
+ * wrapped into [0, 2pi) and, for FP32, rounded to float32 turns).  Waits. */
+xy_status xy_set_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, const double *host);
+
+/* Counters: sweep counter t, exchange counter tau. */
+xy_status xy_get_counters(xy_ctx ctx, uint64_t *t, uint64_t *tau);
+
+/* Storage slot holding each beta-position of a lattice: slot[k], R_l entries. */
+xy_status xy_get_permutation(xy_ctx ctx, int32_t lattice, int32_t *slot);
+
+/* Cumulative accepted Metropolis moves per position index (R_total entries,
+ * attributed to the beta-position the configuration held while it moved). */
+xy_status xy_get_metro_accepts(xy_ctx ctx, int64_t *n_acc);
+
+/*
+ * Launch shape of the FP32 tiled half-sweep for one lattice: a work item is
+ * ty rows (y) by L/2 sites (x) of one colour, streamed over tz planes (z).
+ * ty and tz must divide L, ty*L/2 <= 2048.  grid_cap > 0 makes the launch
+ * persistent with at most grid_cap workgroups (0: one workgroup per item).
+ * Results do not depend on these choices (they only change the order in
+ * which independent same-colour sites are visited); they exist for tuning.
+ * XY_ERR_UNSUPPORTED for FP64 contexts.  Takes effect for later calls.
+ */
+xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap);
+xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
+
+/*
+ * Checkpoint: the whole chain state (angles, permutation, t, tau, seed,
+ * ladders, acceptance counters) as an opaque blob.  With blob == NULL, *size
+ * receives the size needed.  Because randomness is counter-based, a context
+ * restored with xy_set_state continues bit-identically.  Both wait.
+ * xy_set_state requires a context created with the same lattices, ladders,
+ * seed and precision (XY_ERR_STATE otherwise).
+ */
+xy_status xy_get_state(xy_ctx ctx, void *blob, size_t *size);
+xy_status xy_set_state(xy_ctx ctx, const void *blob, size_t size);
+
+/* Message of the last failed call on ctx (or of the last failed xy_init when
+ * ctx is NULL); valid until the next call on the same context. */
+const char *xy_last_error(xy_ctx ctx);
+
+/* Wait for outstanding work and free everything the context owns. */
+void xy_destroy(xy_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XY_H */

@@ -1,0 +1,958 @@
+// Host runtime and C ABI of the XY-model hot path (see include/xy.h).
+//
+// A context owns the device state of a batch of lattices: the colour-split
+// angle buffer, the slot<->beta-position permutation, the device counters,
+// measurement partials and acceptance counters.  Every sweep, measurement
+// and exchange is a short sequence of kernel launches on the context's
+// stream; xy_run captures that sequence once as a HIP graph and replays it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "xy.h"
+#include "xy_kernels.h"
+
+using namespace xy;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Tiling {
+    int TY = 0, TZ = 0, spt = 0;
+};
+
+struct GraphKey {
+    int n_metro = -1, n_or = -1, exch = -1;
+    double *obs = nullptr;
+    bool operator==(const GraphKey &o) const
+    {
+        return n_metro == o.n_metro && n_or == o.n_or && exch == o.exch && obs == o.obs;
+    }
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct xy_ctx_s {
+    // configuration
+    int n_lat = 0;
+    std::vector<int> L, R;
+    std::vector<double> beta;
+    uint64_t seed = 0;
+    int prec = XY_FP32;
+    uint32_t flags = 0;
+    uint32_t k0 = 0, k1 = 0;
+    int R_total = 0, max_R = 0;
+    size_t elem = 4;       // bytes per angle
+    int64_t n_elems = 0;   // total angles
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+
+    // layout
+    std::vector<LatDev> lat_sweep;   // tiled (FP32) or plain (FP64) item spaces
+    std::vector<LatDev> lat_meas;    // standalone measurement item space
+    int items_sweep = 0, items_meas = 0;
+    int spt = 0;
+    size_t lds_bytes = 0;
+    int grid_sweep = 0;
+    size_t partials_cap = 0;
+
+    // device memory
+    void *ang = nullptr;
+    bool own_ang = false;
+    LatDev *d_lat_sweep = nullptr, *d_lat_meas = nullptr;
+    double *d_beta = nullptr;
+    int32_t *d_pos = nullptr, *d_slot_of = nullptr;
+    Ctl *d_ctl = nullptr;
+    double *d_partials = nullptr;
+    double *d_E = nullptr;
+    double *d_obs = nullptr;
+    unsigned long long *d_macc = nullptr, *d_sacc = nullptr;
+    int *d_bad = nullptr;
+    RecheckQueue *d_rq = nullptr;
+    RecheckEntry *d_rq_entries = nullptr;
+    uint32_t rq_capacity = 0;
+
+    // host mirrors
+    uint64_t t = 0, tau = 0;
+    bool e_fresh = false;          // d_E matches the current configurations
+    bool partials_are_sweep = false;
+
+    std::vector<GraphEntry> graphs;
+    std::vector<Tiling> tiles;  // FP32: per-lattice tile choice
+    std::string err;
+};
+
+namespace {
+
+xy_status fail(xy_ctx c, xy_status s, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_init_error = msg;
+    return s;
+}
+
+#define XY_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), XY_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_L(int L) { return L >= 4 && L <= 1024 && (L % 2) == 0; }
+
+std::vector<int> divisors(int L)
+{
+    std::vector<int> d;
+    for (int i = 1; i <= L; ++i)
+        if (L % i == 0) d.push_back(i);
+    return d;
+}
+
+int spt_for(int sites)
+{
+    int s = (sites + kBlock - 1) / kBlock;
+    if (s <= 6) return std::max(s, 1);
+    return 8;
+}
+
+// Default tile of the FP32 kernel: the widest y-tile with at most 5 sites per
+// thread, then the deepest z-chunk that still leaves about 1024 work items
+// per lattice so the 256 CUs stay busy.
+Tiling default_tiling(int L, int R)
+{
+    const int half = L / 2;
+    Tiling t;
+    for (int d : divisors(L))
+        if (d * half <= 5 * kBlock) t.TY = d;
+    if (t.TY == 0) t.TY = 1;
+    const int ny = L / t.TY;
+    t.TZ = 1;
+    for (int d : divisors(L)) {
+        const int64_t items = (int64_t)R * ny * (L / d);
+        if (items >= 1024 && d <= 64) t.TZ = d;
+    }
+    if (t.TZ == 1) {
+        for (int d : divisors(L))
+            if (d <= 8) t.TZ = d;
+    }
+    t.spt = spt_for(t.TY * half);
+    return t;
+}
+
+xy_status sync_stream(xy_ctx c)
+{
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    return XY_OK;
+}
+
+xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_measure)
+{
+    SweepArgs a{};
+    a.n_lat = c->n_lat;
+    a.ang = c->ang;
+    a.beta = c->d_beta;
+    a.pos = c->d_pos;
+    a.ctl = c->d_ctl;
+    a.k0 = c->k0;
+    a.k1 = c->k1;
+    a.colour = colour;
+    a.substep = substep;
+    a.recheck = (c->flags & XY_F_NO_RECHECK) ? 0 : 1;
+    a.partials = c->d_partials;
+    a.macc = c->d_macc;
+    a.rq = c->d_rq;
+    hipError_t e;
+    if (c->prec == XY_FP32) {
+        const bool meas_item_space = (kind == kMeas);
+        a.lats = meas_item_space ? c->d_lat_meas : c->d_lat_sweep;
+        a.total_items = meas_item_space ? c->items_meas : c->items_sweep;
+        const int grid = std::min(a.total_items, c->grid_sweep > 0 ? c->grid_sweep : a.total_items);
+        e = launch_tile_f32(kind, fuse_measure, c->spt, grid, c->lds_bytes, a, c->stream);
+        if (e == hipSuccess && kind == kMetro && a.recheck)
+            e = launch_recheck(c->d_lat_sweep, c->ang, c->d_beta, c->d_pos, colour, c->d_rq, c->d_macc,
+                               c->stream);
+    } else {
+        a.lats = c->d_lat_sweep;
+        a.total_items = c->items_sweep;
+        e = launch_plain_f64(kind, fuse_measure, a.total_items, a, c->stream);
+    }
+    if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return XY_OK;
+}
+
+// Enqueue one sweep; if measure_last, the final half-sweep also produces the
+// measurement partials.
+xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last)
+{
+    const int total = 2 * (n_metro + n_or);
+    int h = 0;
+    for (int s = 0; s < n_metro; ++s)
+        for (int col = 0; col < 2; ++col, ++h) {
+            xy_status st = launch_half(c, kMetro, col, s, measure_last && h == total - 1);
+            if (st) return st;
+        }
+    for (int s = 0; s < n_or; ++s)
+        for (int col = 0; col < 2; ++col, ++h) {
+            xy_status st = launch_half(c, kOver, col, s, measure_last && h == total - 1);
+            if (st) return st;
+        }
+    XY_HIP(c, launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream));
+    return XY_OK;
+}
+
+xy_status enqueue_measure_kernel(xy_ctx c)
+{
+    return launch_half(c, kMeas, 1, 0, false);
+}
+
+const LatDev *meas_layout_dev(xy_ctx c, bool from_sweep)
+{
+    if (c->prec == XY_FP64) return c->d_lat_sweep;
+    return from_sweep ? c->d_lat_sweep : c->d_lat_meas;
+}
+
+xy_status enqueue_finalize(xy_ctx c, bool from_sweep_partials, double *obs, int use_ring,
+                           bool do_sum, bool do_exchange)
+{
+    XY_HIP(c, launch_finalize(meas_layout_dev(c, from_sweep_partials), c->n_lat, c->max_R,
+                              c->d_partials, c->d_beta, c->d_pos, c->d_slot_of, c->d_E, obs, use_ring,
+                              (int64_t)5 * c->R_total, do_sum ? 1 : 0, do_exchange ? 1 : 0,
+                              c->d_sacc, c->d_ctl, c->k0, c->k1, c->d_bad, c->stream));
+    return XY_OK;
+}
+
+xy_status check_bad(xy_ctx c)
+{
+    int bad = 0;
+    XY_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, XY_ERR_STATE, "non-finite energy or magnetisation in the device state");
+    return XY_OK;
+}
+
+void free_graphs(xy_ctx c)
+{
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+void free_all(xy_ctx c)
+{
+    if (!c) return;
+    if (c->stream || c->cap_stream) (void)hipDeviceSynchronize();
+    free_graphs(c);
+    if (c->own_ang && c->ang) (void)hipFree(c->ang);
+    void *ptrs[] = {c->d_lat_sweep, c->d_lat_meas, c->d_beta, c->d_pos, c->d_slot_of, c->d_ctl,
+                    c->d_partials, c->d_E, c->d_obs, c->d_macc, c->d_sacc, c->d_bad,
+                    c->d_rq, c->d_rq_entries};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+}
+
+xy_status validate(const xy_config *cfg)
+{
+    if (!cfg) return fail(nullptr, XY_ERR_ARG, "config is NULL");
+    if (cfg->n_lattices < 1 || cfg->n_lattices > 64)
+        return fail(nullptr, XY_ERR_ARG, "n_lattices must be in [1, 64]");
+    if (!cfg->L || !cfg->n_replicas || !cfg->beta)
+        return fail(nullptr, XY_ERR_ARG, "L, n_replicas and beta must be non-NULL");
+    if (cfg->prec != XY_FP32 && cfg->prec != XY_FP64)
+        return fail(nullptr, XY_ERR_ARG, "prec must be XY_FP32 or XY_FP64");
+    if (cfg->start != XY_START_RANDOM && cfg->start != XY_START_ORDERED)
+        return fail(nullptr, XY_ERR_ARG, "start must be XY_START_RANDOM or XY_START_ORDERED");
+    int64_t off = 0;
+    for (int l = 0; l < cfg->n_lattices; ++l) {
+        const int L = cfg->L[l], R = cfg->n_replicas[l];
+        if (!valid_L(L))
+            return fail(nullptr, XY_ERR_ODD_L,
+                        "lattice " + std::to_string(l) + ": L = " + std::to_string(L) +
+                            " must be even with 4 <= L <= 1024");
+        if (R < 1 || R > 65535)
+            return fail(nullptr, XY_ERR_ARG, "lattice " + std::to_string(l) + ": n_replicas must be in [1, 65535]");
+        for (int k = 0; k < R; ++k) {
+            const double b = cfg->beta[off + k];
+            if (!std::isfinite(b) || b < 0.0)
+                return fail(nullptr, XY_ERR_ARG, "beta must be finite and >= 0");
+            if (k > 0 && !(b > cfg->beta[off + k - 1]))
+                return fail(nullptr, XY_ERR_ARG,
+                            "lattice " + std::to_string(l) + ": beta ladder must be strictly ascending");
+        }
+        off += R;
+    }
+    return XY_OK;
+}
+
+int64_t total_elems(const xy_config *cfg)
+{
+    int64_t n = 0;
+    for (int l = 0; l < cfg->n_lattices; ++l)
+        n += (int64_t)cfg->n_replicas[l] * (int64_t)cfg->L[l] * cfg->L[l] * cfg->L[l];
+    return n;
+}
+
+template <typename T>
+xy_status dev_alloc(xy_ctx c, T **p, size_t count)
+{
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? XY_ERR_OOM : XY_ERR_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return XY_OK;
+}
+
+// Build the item spaces.  FP32: tiled sweep (TY x L/2 x TZ per item) and a
+// measurement space with the same tiles; FP64: one item per kBlock sites of
+// a colour of a slot, for every kernel.
+void build_layout(xy_ctx c)
+{
+    int64_t base = 0;
+    int pos_base = 0, item_s = 0, item_m = 0;
+    c->spt = 1;
+    int max_rowbuf = 0;
+    c->lat_sweep.clear();
+    c->lat_meas.clear();
+    for (int l = 0; l < c->n_lat; ++l) {
+        LatDev d{};
+        d.L = c->L[l];
+        d.half = d.L / 2;
+        d.R = c->R[l];
+        d.lat = l;
+        d.base = base;
+        d.N = (int64_t)d.L * d.L * d.L;
+        d.pos_base = pos_base;
+        if (c->prec == XY_FP32) {
+            if ((int)c->tiles.size() <= l) c->tiles.push_back(default_tiling(d.L, d.R));
+            const Tiling t = c->tiles[l];
+            d.TY = t.TY;
+            d.TZ = t.TZ;
+            d.ny = d.L / t.TY;
+            d.nz = d.L / t.TZ;
+            d.items_per_slot = d.ny * d.nz;
+            c->spt = std::max(c->spt, t.spt);
+            max_rowbuf = std::max(max_rowbuf, (t.TY + 2) * d.half);
+        } else {
+            d.TY = d.TZ = d.ny = d.nz = 0;
+            d.items_per_slot = (int)((d.N / 2 + kBlock - 1) / kBlock);
+        }
+        d.item_base = item_s;
+        item_s += d.R * d.items_per_slot;
+        c->lat_sweep.push_back(d);
+        LatDev m = d;
+        m.item_base = item_m;
+        item_m += m.R * m.items_per_slot;
+        c->lat_meas.push_back(m);
+        base += (int64_t)d.R * d.N;
+        pos_base += d.R;
+    }
+    c->items_sweep = item_s;
+    c->items_meas = item_m;
+    c->lds_bytes = (size_t)2 * max_rowbuf * 2 * sizeof(float);  // two planes of (cos, sin)
+}
+
+// Re-derive item spaces after a tiling change and upload them.  Partials
+// are indexed by item, so grow that buffer if needed; graphs bake the old
+// launch shapes in and are dropped.
+xy_status relayout(xy_ctx c)
+{
+    build_layout(c);
+    const int n_items_max = std::max(c->items_sweep, c->items_meas);
+    if ((size_t)3 * n_items_max > c->partials_cap) {
+        XY_HIP(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_partials);
+        c->d_partials = nullptr;
+        xy_status st = dev_alloc(c, &c->d_partials, (size_t)3 * n_items_max);
+        if (st) return st;
+        c->partials_cap = (size_t)3 * n_items_max;
+    }
+    XY_HIP(c, hipMemcpyAsync(c->d_lat_sweep, c->lat_sweep.data(), sizeof(LatDev) * c->n_lat,
+                             hipMemcpyHostToDevice, c->stream));
+    XY_HIP(c, hipMemcpyAsync(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat,
+                             hipMemcpyHostToDevice, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    free_graphs(c);
+    c->e_fresh = false;
+    return XY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t xy_angles_bytes(const xy_config *cfg)
+{
+    if (validate(cfg) != XY_OK) return 0;
+    return (size_t)total_elems(cfg) * (cfg->prec == XY_FP32 ? 4 : 8);
+}
+
+xy_status xy_init(const xy_config *cfg, xy_ctx *out)
+{
+    if (!out) return fail(nullptr, XY_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    xy_status st = validate(cfg);
+    if (st) return st;
+    if (total_elems(cfg) > ((int64_t)1 << 36))
+        return fail(nullptr, XY_ERR_ARG, "total number of angles exceeds 2^36");
+
+    xy_ctx c = new (std::nothrow) xy_ctx_s();
+    if (!c) return fail(nullptr, XY_ERR_OOM, "host allocation failed");
+    c->n_lat = cfg->n_lattices;
+    c->L.assign(cfg->L, cfg->L + c->n_lat);
+    c->R.assign(cfg->n_replicas, cfg->n_replicas + c->n_lat);
+    for (int l = 0; l < c->n_lat; ++l) {
+        c->R_total += c->R[l];
+        c->max_R = std::max(c->max_R, c->R[l]);
+    }
+    c->beta.assign(cfg->beta, cfg->beta + c->R_total);
+    c->seed = cfg->seed;
+    c->k0 = (uint32_t)(cfg->seed & 0xffffffffu);
+    c->k1 = (uint32_t)(cfg->seed >> 32);
+    c->prec = cfg->prec;
+    c->flags = cfg->flags;
+    c->elem = (c->prec == XY_FP32) ? 4 : 8;
+    c->n_elems = total_elems(cfg);
+    c->stream = (hipStream_t)cfg->stream;
+    build_layout(c);
+
+    auto bail = [&](xy_status s) {
+        g_init_error = c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
+        c->err = "no HIP device available";
+        return bail(XY_ERR_HIP);
+    }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->err = "hipStreamCreateWithFlags failed";
+        return bail(XY_ERR_HIP);
+    }
+    if (cfg->angles_dev) {
+        c->ang = cfg->angles_dev;
+        c->own_ang = false;
+    } else {
+        if ((st = dev_alloc(c, (char **)&c->ang, (size_t)c->n_elems * c->elem))) return bail(st);
+        c->own_ang = true;
+    }
+    const int n_items_max = std::max(c->items_sweep, c->items_meas);
+    if ((st = dev_alloc(c, &c->d_lat_sweep, c->n_lat)) || (st = dev_alloc(c, &c->d_lat_meas, c->n_lat)) ||
+        (st = dev_alloc(c, &c->d_beta, c->R_total)) || (st = dev_alloc(c, &c->d_pos, c->R_total)) ||
+        (st = dev_alloc(c, &c->d_slot_of, c->R_total)) || (st = dev_alloc(c, &c->d_ctl, 1)) ||
+        (st = dev_alloc(c, &c->d_partials, (size_t)3 * n_items_max)) ||
+        (st = dev_alloc(c, &c->d_E, c->R_total)) || (st = dev_alloc(c, &c->d_obs, (size_t)5 * c->R_total)) ||
+        (st = dev_alloc(c, &c->d_macc, c->R_total)) || (st = dev_alloc(c, &c->d_sacc, c->R_total)) ||
+        (st = dev_alloc(c, &c->d_bad, 1)))
+        return bail(st);
+    // Near-threshold queue: about 2e-5 of a half-sweep's sites land in the band;
+    // capacity allows for 1e-3 of the largest lattice's half-sweep.
+    {
+        int64_t half_sweep_sites = 0;
+        for (int l = 0; l < c->n_lat; ++l) half_sweep_sites += (int64_t)c->R[l] * c->lat_sweep[l].N / 2;
+        c->rq_capacity = (uint32_t)std::min<int64_t>(std::max<int64_t>(4096, half_sweep_sites / 1000), 1 << 22);
+        if ((st = dev_alloc(c, &c->d_rq, 1)) || (st = dev_alloc(c, &c->d_rq_entries, c->rq_capacity)))
+            return bail(st);
+    }
+
+    c->partials_cap = (size_t)3 * n_items_max;
+    std::vector<int32_t> ident(c->R_total);
+    {
+        int p = 0;
+        for (int l = 0; l < c->n_lat; ++l)
+            for (int r = 0; r < c->R[l]; ++r) ident[p++] = r;
+    }
+    std::vector<unsigned long long> zeros(c->R_total, 0ull);
+    Ctl ctl{};
+    int zero = 0;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(c->d_lat_sweep, c->lat_sweep.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_beta, c->beta.data(), sizeof(double) * c->R_total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_pos, ident.data(), sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_slot_of, ident.data(), sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_macc, zeros.data(), sizeof(unsigned long long) * c->R_total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_sacc, zeros.data(), sizeof(unsigned long long) * c->R_total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        RecheckQueue q{0u, 0u, c->rq_capacity, 0u, c->d_rq_entries};
+        e = hipMemcpy(c->d_rq, &q, sizeof(q), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        c->err = std::string("hipMemcpy: ") + hipGetErrorString(e);
+        return bail(XY_ERR_HIP);
+    }
+    e = launch_init(c->prec == XY_FP32, cfg->start == XY_START_ORDERED, c->d_lat_sweep, c->n_lat,
+                    c->n_elems, c->ang, c->k0, c->k1, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("init kernel: ") + hipGetErrorString(e);
+        return bail(XY_ERR_HIP);
+    }
+    *out = c;
+    return XY_OK;
+}
+
+xy_status xy_sweep(xy_ctx c, int32_t n_metro, int32_t n_or)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || n_metro > 255 || n_or > 65535)
+        return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
+    if (c->t >= 0xffffffffull) return fail(c, XY_ERR_STATE, "sweep counter would overflow 32 bits");
+    xy_status st = enqueue_sweep(c, n_metro, n_or, false);
+    if (st) return st;
+    c->t += 1;
+    c->e_fresh = false;
+    return XY_OK;
+}
+
+xy_status xy_sweep_profiled(xy_ctx c, int32_t n_metro, int32_t n_or, double *ms, int32_t *launches)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!ms || !launches) return fail(c, XY_ERR_ARG, "ms and launches must be non-NULL");
+    if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || n_metro > 255 || n_or > 65535)
+        return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
+    if (c->t >= 0xffffffffull) return fail(c, XY_ERR_STATE, "sweep counter would overflow 32 bits");
+    const int n_half = 2 * (n_metro + n_or);
+    std::vector<hipEvent_t> ev(2 * n_half + 2, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(c, XY_ERR_HIP, "hipEventCreate failed");
+        }
+    xy_status st = XY_OK;
+    int h = 0;
+    for (int s = 0; s < n_metro && !st; ++s)
+        for (int col = 0; col < 2 && !st; ++col, ++h) {
+            (void)hipEventRecord(ev[2 * h], c->stream);
+            st = launch_half(c, kMetro, col, s, false);
+            (void)hipEventRecord(ev[2 * h + 1], c->stream);
+        }
+    for (int s = 0; s < n_or && !st; ++s)
+        for (int col = 0; col < 2 && !st; ++col, ++h) {
+            (void)hipEventRecord(ev[2 * h], c->stream);
+            st = launch_half(c, kOver, col, s, false);
+            (void)hipEventRecord(ev[2 * h + 1], c->stream);
+        }
+    if (!st) {
+        (void)hipEventRecord(ev[2 * n_half], c->stream);
+        hipError_t e = launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream);
+        (void)hipEventRecord(ev[2 * n_half + 1], c->stream);
+        if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
+    }
+    if (!st && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, XY_ERR_HIP, "sync failed");
+    if (!st) {
+        ms[0] = ms[1] = ms[2] = 0.0;
+        launches[0] = launches[1] = launches[2] = 0;
+        for (int i = 0; i < n_half; ++i) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            const int kind = i < 2 * n_metro ? 0 : 1;
+            ms[kind] += t;
+            launches[kind] += 1;
+        }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[2 * n_half], ev[2 * n_half + 1]);
+        ms[2] = t;
+        launches[2] = 1;
+        c->t += 1;
+        c->e_fresh = false;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return st;
+}
+
+xy_status xy_measure(xy_ctx c, double *obs, int32_t obs_on_device)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!obs) return fail(c, XY_ERR_ARG, "obs is NULL");
+    xy_status st = enqueue_measure_kernel(c);
+    if (st) return st;
+    double *dst = obs_on_device ? obs : c->d_obs;
+    if ((st = enqueue_finalize(c, false, dst, 0, true, false))) return st;
+    c->e_fresh = true;
+    if (!obs_on_device) {
+        XY_HIP(c, hipMemcpyAsync(obs, c->d_obs, sizeof(double) * 5 * c->R_total, hipMemcpyDeviceToHost,
+                                 c->stream));
+        return check_bad(c);
+    }
+    return XY_OK;
+}
+
+xy_status xy_exchange(xy_ctx c, int64_t *n_acc)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (c->tau >= 0xffffffffull) return fail(c, XY_ERR_STATE, "exchange counter would overflow 32 bits");
+    xy_status st;
+    if (!c->e_fresh) {
+        if ((st = enqueue_measure_kernel(c))) return st;
+        if ((st = enqueue_finalize(c, false, nullptr, 0, true, false))) return st;
+        c->e_fresh = true;
+    }
+    if ((st = enqueue_finalize(c, false, nullptr, 0, false, true))) return st;
+    XY_HIP(c, launch_tick(c->d_ctl, 0u, 1u, 0u, 0, c->stream));
+    c->tau += 1;
+    if (n_acc) {
+        std::vector<unsigned long long> v(c->R_total);
+        XY_HIP(c, hipMemcpyAsync(v.data(), c->d_sacc, sizeof(unsigned long long) * c->R_total,
+                                 hipMemcpyDeviceToHost, c->stream));
+        XY_HIP(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < c->R_total; ++i) n_acc[i] = (int64_t)v[i];
+    }
+    return XY_OK;
+}
+
+xy_status xy_run(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int32_t exchange_every,
+                 double *obs_dev)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (n_sweeps < 0 || exchange_every < 0) return fail(c, XY_ERR_ARG, "n_sweeps and exchange_every must be >= 0");
+    if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || n_metro > 255 || n_or > 65535)
+        return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
+    if (c->t + (uint64_t)n_sweeps > 0xffffffffull || c->tau + (uint64_t)n_sweeps > 0xffffffffull)
+        return fail(c, XY_ERR_STATE, "counters would overflow 32 bits");
+    if (n_sweeps == 0) return XY_OK;
+
+    // Two captured graphs: sweep + measure, and sweep + measure + exchange.
+    auto get_graph = [&](int exch, hipGraphExec_t *exec) -> xy_status {
+        GraphKey key{n_metro, n_or, exch, obs_dev};
+        for (auto &g : c->graphs)
+            if (g.key == key) {
+                *exec = g.exec;
+                return XY_OK;
+            }
+        GraphEntry g;
+        g.key = key;
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        XY_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        xy_status st = enqueue_sweep(c, n_metro, n_or, true);
+        if (!st) st = enqueue_finalize(c, true, obs_dev, 1, true, exch != 0);
+        if (!st) {
+            hipError_t e = launch_tick(c->d_ctl, 0u, exch ? 1u : 0u, obs_dev ? 1u : 0u, 0, c->cap_stream);
+            if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        c->stream = user;
+        if (st) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(c, XY_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        g.graph = graph;
+        c->graphs.push_back(g);
+        *exec = g.exec;
+        return XY_OK;
+    };
+
+    hipGraphExec_t g_plain = nullptr, g_exch = nullptr;
+    xy_status st;
+    if ((st = get_graph(0, &g_plain))) return st;
+    if (exchange_every > 0 && (st = get_graph(1, &g_exch))) return st;
+    XY_HIP(c, launch_tick(c->d_ctl, 0u, 0u, 0u, 1, c->stream));  // ring <- 0
+    for (int s = 0; s < n_sweeps; ++s) {
+        const bool ex = exchange_every > 0 && ((s + 1) % exchange_every) == 0;
+        XY_HIP(c, hipGraphLaunch(ex ? g_exch : g_plain, c->stream));
+        c->t += 1;
+        if (ex) c->tau += 1;
+    }
+    c->e_fresh = true;
+    return XY_OK;
+}
+
+xy_status xy_set_tiling(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (c->prec != XY_FP32) return fail(c, XY_ERR_UNSUPPORTED, "tiling applies to FP32 contexts only");
+    if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
+    const int L = c->L[lattice];
+    if (ty < 1 || tz < 1 || L % ty != 0 || L % tz != 0)
+        return fail(c, XY_ERR_ARG, "ty and tz must divide L");
+    if (ty * (L / 2) > 8 * kBlock) return fail(c, XY_ERR_ARG, "ty * L/2 must be <= 2048");
+    if (grid_cap < 0) return fail(c, XY_ERR_ARG, "grid_cap must be >= 0");
+    Tiling t;
+    t.TY = ty;
+    t.TZ = tz;
+    t.spt = spt_for(ty * (L / 2));
+    c->tiles[lattice] = t;
+    c->grid_sweep = grid_cap;
+    return relayout(c);
+}
+
+xy_status xy_get_tiling(xy_ctx c, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
+    if (c->prec != XY_FP32) {
+        if (ty) *ty = 0;
+        if (tz) *tz = 0;
+        if (grid_cap) *grid_cap = 0;
+        return XY_OK;
+    }
+    if (ty) *ty = c->tiles[lattice].TY;
+    if (tz) *tz = c->tiles[lattice].TZ;
+    if (grid_cap) *grid_cap = c->grid_sweep;
+    return XY_OK;
+}
+
+xy_status xy_get_counters(xy_ctx c, uint64_t *t, uint64_t *tau)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (t) *t = c->t;
+    if (tau) *tau = c->tau;
+    return XY_OK;
+}
+
+xy_status xy_get_permutation(xy_ctx c, int32_t lattice, int32_t *slot)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (lattice < 0 || lattice >= c->n_lat || !slot) return fail(c, XY_ERR_ARG, "bad lattice or NULL slot");
+    XY_HIP(c, hipMemcpyAsync(slot, c->d_slot_of + c->lat_sweep[lattice].pos_base,
+                             sizeof(int32_t) * c->R[lattice], hipMemcpyDeviceToHost, c->stream));
+    return sync_stream(c);
+}
+
+xy_status xy_get_metro_accepts(xy_ctx c, int64_t *n_acc)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!n_acc) return fail(c, XY_ERR_ARG, "n_acc is NULL");
+    std::vector<unsigned long long> v(c->R_total);
+    XY_HIP(c, hipMemcpyAsync(v.data(), c->d_macc, sizeof(unsigned long long) * c->R_total,
+                             hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->R_total; ++i) n_acc[i] = (int64_t)v[i];
+    return XY_OK;
+}
+
+// Angle access by (lattice, beta-position) through the slot permutation.
+static xy_status slot_of_position(xy_ctx c, int lattice, int beta_pos, int *slot)
+{
+    if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
+    if (beta_pos < 0 || beta_pos >= c->R[lattice]) return fail(c, XY_ERR_ARG, "beta_pos out of range");
+    int32_t s = 0;
+    XY_HIP(c, hipMemcpyAsync(&s, c->d_slot_of + c->lat_sweep[lattice].pos_base + beta_pos,
+                             sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    *slot = s;
+    return XY_OK;
+}
+
+xy_status xy_get_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!host) return fail(c, XY_ERR_ARG, "host is NULL");
+    int slot = 0;
+    xy_status st = slot_of_position(c, lattice, beta_pos, &slot);
+    if (st) return st;
+    const LatDev &d = c->lat_sweep[lattice];
+    std::vector<char> raw((size_t)d.N * c->elem);
+    XY_HIP(c, hipMemcpyAsync(raw.data(), (char *)c->ang + (size_t)(d.base + (int64_t)slot * d.N) * c->elem,
+                             raw.size(), hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    const int L = d.L, half = d.half;
+    const double twopi = 6.283185307179586476925286766559;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int col = (x + y + z) & 1;
+                const int64_t src = (int64_t)col * (d.N / 2) + ((int64_t)z * L + y) * half + (x >> 1);
+                const int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
+                host[i] = (c->prec == XY_FP32) ? (double)((const float *)raw.data())[src] * twopi
+                                               : ((const double *)raw.data())[src];
+            }
+    return XY_OK;
+}
+
+xy_status xy_set_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, const double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!host) return fail(c, XY_ERR_ARG, "host is NULL");
+    int slot = 0;
+    xy_status st = slot_of_position(c, lattice, beta_pos, &slot);
+    if (st) return st;
+    const LatDev &d = c->lat_sweep[lattice];
+    const int L = d.L, half = d.half;
+    const double twopi = 6.283185307179586476925286766559;
+    std::vector<char> raw((size_t)d.N * c->elem);
+    for (int64_t i = 0; i < d.N; ++i)
+        if (!std::isfinite(host[i])) return fail(c, XY_ERR_ARG, "angles must be finite");
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int col = (x + y + z) & 1;
+                const int64_t dst = (int64_t)col * (d.N / 2) + ((int64_t)z * L + y) * half + (x >> 1);
+                const int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
+                double v = std::fmod(host[i], twopi);
+                if (v < 0.0) v += twopi;
+                if (v >= twopi) v = 0.0;
+                if (c->prec == XY_FP32) {
+                    float tf = (float)(v / twopi);
+                    if (!(tf < 1.0f)) tf = 0.0f;
+                    ((float *)raw.data())[dst] = tf;
+                } else {
+                    ((double *)raw.data())[dst] = v;
+                }
+            }
+    XY_HIP(c, hipMemcpyAsync((char *)c->ang + (size_t)(d.base + (int64_t)slot * d.N) * c->elem, raw.data(),
+                             raw.size(), hipMemcpyHostToDevice, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    c->e_fresh = false;
+    return XY_OK;
+}
+
+// --- checkpoint blob -------------------------------------------------------
+namespace {
+struct BlobHeader {
+    char magic[8];
+    uint32_t version, n_lat;
+    int32_t prec, R_total;
+    uint64_t seed, t, tau;
+    int64_t n_elems;
+};
+constexpr char kMagic[8] = {'X', 'Y', 'S', 'T', 'A', 'T', 'E', '1'};
+
+size_t blob_size(xy_ctx c)
+{
+    return sizeof(BlobHeader) + sizeof(int32_t) * 2 * c->n_lat + sizeof(double) * c->R_total +
+           sizeof(int32_t) * 2 * c->R_total + sizeof(unsigned long long) * 2 * c->R_total +
+           (size_t)c->n_elems * c->elem;
+}
+}  // namespace
+
+xy_status xy_get_state(xy_ctx c, void *blob, size_t *size)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!size) return fail(c, XY_ERR_ARG, "size is NULL");
+    const size_t need = blob_size(c);
+    if (!blob) {
+        *size = need;
+        return XY_OK;
+    }
+    if (*size < need) return fail(c, XY_ERR_ARG, "blob too small");
+    char *p = (char *)blob;
+    BlobHeader h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.n_lat = (uint32_t)c->n_lat;
+    h.prec = c->prec;
+    h.R_total = c->R_total;
+    h.seed = c->seed;
+    h.t = c->t;
+    h.tau = c->tau;
+    h.n_elems = c->n_elems;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    std::memcpy(p, c->L.data(), sizeof(int32_t) * c->n_lat);
+    p += sizeof(int32_t) * c->n_lat;
+    std::memcpy(p, c->R.data(), sizeof(int32_t) * c->n_lat);
+    p += sizeof(int32_t) * c->n_lat;
+    std::memcpy(p, c->beta.data(), sizeof(double) * c->R_total);
+    p += sizeof(double) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(p, c->d_pos, sizeof(int32_t) * c->R_total, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(int32_t) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(p, c->d_slot_of, sizeof(int32_t) * c->R_total, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(int32_t) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(p, c->d_macc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(unsigned long long) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(p, c->d_sacc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(unsigned long long) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(p, c->ang, (size_t)c->n_elems * c->elem, hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    *size = need;
+    return XY_OK;
+}
+
+xy_status xy_set_state(xy_ctx c, const void *blob, size_t size)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!blob) return fail(c, XY_ERR_ARG, "blob is NULL");
+    if (size != blob_size(c)) return fail(c, XY_ERR_STATE, "blob size does not match this context");
+    const char *p = (const char *)blob;
+    BlobHeader h;
+    std::memcpy(&h, p, sizeof h);
+    p += sizeof h;
+    if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) return fail(c, XY_ERR_STATE, "not a state blob");
+    if ((int)h.n_lat != c->n_lat || h.prec != c->prec || h.R_total != c->R_total || h.seed != c->seed ||
+        h.n_elems != c->n_elems)
+        return fail(c, XY_ERR_STATE, "blob was written by a context with another configuration");
+    if (std::memcmp(p, c->L.data(), sizeof(int32_t) * c->n_lat) != 0 ||
+        std::memcmp(p + sizeof(int32_t) * c->n_lat, c->R.data(), sizeof(int32_t) * c->n_lat) != 0 ||
+        std::memcmp(p + sizeof(int32_t) * 2 * c->n_lat, c->beta.data(), sizeof(double) * c->R_total) != 0)
+        return fail(c, XY_ERR_STATE, "blob lattices or ladders differ from this context");
+    p += sizeof(int32_t) * 2 * c->n_lat + sizeof(double) * c->R_total;
+    // validate the permutation before touching device state
+    {
+        const int32_t *pos = (const int32_t *)p, *slot_of = pos + c->R_total;
+        for (int l = 0; l < c->n_lat; ++l) {
+            const int pb = c->lat_sweep[l].pos_base;
+            for (int r = 0; r < c->R[l]; ++r) {
+                const int32_t k = pos[pb + r];
+                if (k < 0 || k >= c->R[l] || slot_of[pb + k] != r)
+                    return fail(c, XY_ERR_STATE, "blob permutation is not a bijection");
+            }
+        }
+    }
+    if (h.t > 0xffffffffull || h.tau > 0xffffffffull) return fail(c, XY_ERR_STATE, "blob counters out of range");
+    XY_HIP(c, hipMemcpyAsync(c->d_pos, p, sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(int32_t) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(c->d_slot_of, p, sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(int32_t) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(c->d_macc, p, sizeof(unsigned long long) * c->R_total, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(unsigned long long) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(c->d_sacc, p, sizeof(unsigned long long) * c->R_total, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(unsigned long long) * c->R_total;
+    XY_HIP(c, hipMemcpyAsync(c->ang, p, (size_t)c->n_elems * c->elem, hipMemcpyHostToDevice, c->stream));
+    Ctl ctl{(uint32_t)h.t, (uint32_t)h.tau, 0u, 0u};
+    XY_HIP(c, hipMemcpyAsync(c->d_ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    c->t = h.t;
+    c->tau = h.tau;
+    c->e_fresh = false;
+    return XY_OK;
+}
+
+const char *xy_last_error(xy_ctx c)
+{
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+void xy_destroy(xy_ctx c)
+{
+    if (!c) return;
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+"""GPU path against the CPU FP64 oracle, through the C ABI.
+
+Same seeded inputs on both sides; the oracle's input is always the GPU's own
+state read back through xy_get_angles (exact promotion of float32 turns to
+float64 radians), so each comparison covers exactly one step.
+
+Tolerances:
+  FP64: circular angle distance <= 1e-12 rad; no decision flips expected.
+  FP32 (per half-sweep): <= 2e-5 rad where decisions agree; over-relaxation
+        max(2e-5, 16 * 2^-24 * 6 / |h|); a Metropolis decision may differ only
+        where |u - exp(-beta dE)| < 1e-6 (dE in float64 from the same state).
+  Reductions on an identical state: |dE| <= 1e-9 N (FP64), 1e-6 N (FP32);
+        |d|m|| <= 1e-12 (FP64), 1e-6 (FP32).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.philox_py as P
+from gpu_util import circ, colour_mask, field_numpy, gpu_states
+
+pytestmark = pytest.mark.gpu
+
+
+def make(L, betas, seed, prec, start="random", **kw):
+    from paper_1211_0780_amd.sim import Sim
+    return Sim(L, betas, seed=seed, prec=prec, start=start, **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_start_matches_oracle_bit_exact(gpu, prec):
+    L, R, seed = 8, 3, 0xABCDEF0123
+    s = make(L, [0.1, 0.2, 0.3], seed, prec)
+    ref = oracle.init(L, R, seed, 0)
+    assert np.array_equal(gpu_states(s), ref)
+
+
+def test_random_start_batch_uses_lattice_index(gpu):
+    s = make([6, 4], [[0.1, 0.2], [0.3]], 5, "fp32")
+    assert np.array_equal(gpu_states(s, 0), oracle.init(6, 2, 5, 0))
+    assert np.array_equal(gpu_states(s, 1), oracle.init(4, 1, 5, 1))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L", [4, 8, 12])
+def test_beta_zero_metropolis_is_closed_form(gpu, prec, L):
+    """beta = 0: every proposal is accepted, theta = 2 pi U(r0) exactly."""
+    seed = 77
+    s = make(L, [0.0], seed, prec)
+    s.sweep(1, 0)
+    got = s.get_angles(0, 0)
+    key = P.key_of(seed)
+    want = np.array([2 * np.pi * P.uniform(P.philox4x32_10(P.counter(i, 0, 0, 0, P.PHASE_METRO, 0), key)[0])
+                     for i in range(L ** 3)])
+    assert np.array_equal(got, want)
+    assert s.metro_accepts()[0] == L ** 3
+
+
+def _metro_flip_ok(start, L, beta, seed, t, lat, k, sub, colour, got, ref):
+    """Sites where GPU and oracle disagree about acceptance must be within
+    1e-6 of the threshold; returns the mask of agreeing sites."""
+    m = colour_mask(L, colour)
+    key = P.key_of(seed)
+    hx, hy = field_numpy(start, L)
+    idx = np.flatnonzero(m)
+    props = np.empty(idx.size)
+    us = np.empty(idx.size)
+    for n, i in enumerate(idx):
+        r = P.philox4x32_10(P.counter(int(i), t, lat, k, P.PHASE_METRO, sub), key)
+        props[n] = 2 * np.pi * P.uniform(r[0])
+        us[n] = P.uniform(r[1])
+    th = start[idx]
+    dE = (np.cos(th) - np.cos(props)) * hx[idx] + (np.sin(th) - np.sin(props)) * hy[idx]
+    p = np.exp(-beta * dE)
+    acc_gpu = circ(got[idx], props) < 1e-6
+    acc_ref = circ(ref[idx], props) < 1e-6
+    flips = acc_gpu != acc_ref
+    assert np.all(np.abs(us[flips] - p[flips]) < 1e-6), (np.abs(us[flips] - p[flips]))
+    agree = np.ones(L ** 3, dtype=bool)
+    agree[idx[flips]] = False
+    return agree, int(flips.sum())
+
+
+def _or_bound(start, L, prec):
+    if prec == "fp64":
+        return 1e-12
+    hx, hy = field_numpy(start, L)
+    return np.maximum(2e-5, 16 * 2.0 ** -24 * 6 / np.maximum(np.hypot(hx, hy), 1e-30))
+
+
+@pytest.mark.parametrize("prec,L,R,tiling", [
+    ("fp64", 8, 1, None),
+    ("fp64", 6, 2, None),
+    ("fp32", 8, 1, None),
+    ("fp32", 16, 3, (4, 2)),     # several y-tiles and z-chunks
+    ("fp32", 24, 2, None),       # 288 sites per plane: ragged last wave
+    ("fp32", 12, 2, (12, 3)),
+])
+def test_half_sweep_parity(gpu, prec, L, R, tiling):
+    """One Metropolis substep, then one over-relaxation substep, each colour
+    checked against the oracle's half-sweep from the same state."""
+    betas = list(np.linspace(0.40, 0.50, R))
+    seed = 1234
+    s = make(L, betas, seed, prec)
+    if tiling:
+        s_ty, s_tz = tiling
+        from paper_1211_0780_amd import _capi as C
+        C.check(C.lib().xy_set_tiling(s._ctx, 0, s_ty, s_tz, 0), s._ctx)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    n_flips = 0
+    for sweep in range(3):
+        t = s.counters()[0]
+        before = gpu_states(s)
+        s.sweep(1, 0)
+        after = gpu_states(s)
+        for k in range(R):
+            # colour 0 from the GPU start; colour 1 from GPU colour 0 + start colour 1
+            ref = before[k].copy()
+            oracle.metro_half(ref, L, betas[k], seed, t, 0, k, 0, 0)
+            m0 = colour_mask(L, 0)
+            agree, nf = _metro_flip_ok(before[k], L, betas[k], seed, t, 0, k, 0, 0, after[k], ref)
+            n_flips += nf
+            assert np.max(circ(after[k], ref)[m0 & agree]) <= tol
+            mid = before[k].copy()
+            mid[m0] = after[k][m0]
+            ref = mid.copy()
+            oracle.metro_half(ref, L, betas[k], seed, t, 0, k, 0, 1)
+            m1 = colour_mask(L, 1)
+            agree, nf = _metro_flip_ok(mid, L, betas[k], seed, t, 0, k, 0, 1, after[k], ref)
+            n_flips += nf
+            assert np.max(circ(after[k], ref)[m1 & agree]) <= tol
+        before = gpu_states(s)
+        s.sweep(0, 1)
+        after = gpu_states(s)
+        for k in range(R):
+            ref = before[k].copy()
+            oracle.or_half(ref, L, 0)
+            m0 = colour_mask(L, 0)
+            bound = _or_bound(before[k], L, prec)
+            assert np.all((circ(after[k], ref) <= bound)[m0])
+            mid = before[k].copy()
+            mid[m0] = after[k][m0]
+            ref = mid.copy()
+            oracle.or_half(ref, L, 1)
+            m1 = colour_mask(L, 1)
+            bound = _or_bound(mid, L, prec)
+            assert np.all((circ(after[k], ref) <= bound)[m1])
+    if prec == "fp64":
+        assert n_flips == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_sweeps_match_oracle(gpu, prec):
+    """configs[0]-like chain (L = 8, beta = 0.4542, 1 + 1): ten sweeps, each
+    re-started from the GPU state, against the oracle's sweep."""
+    L, seed, beta = 8, 1, 0.4542
+    s = make(L, [beta], seed, prec)
+    errs = []
+    for _ in range(10):
+        t = s.counters()[0]
+        before = s.get_angles()
+        s.sweep(1, 1)
+        ref = before.reshape(1, -1).copy()
+        oracle.sweep(ref, L, [beta], seed, t, 0, 1, 1)
+        errs.append(np.max(circ(s.get_angles(), ref[0])))
+    if prec == "fp64":
+        assert max(errs) <= 1e-12
+    else:
+        # errors propagate through neighbours across four half-sweeps; report-level bound
+        assert np.median(errs) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_measure_matches_oracle(gpu, prec):
+    L, R = 16, 3
+    s = make(L, [0.3, 0.45, 0.6], 11, prec)
+    for _ in range(3):
+        s.sweep(1, 2)
+    obs = s.measure()
+    N = L ** 3
+    for k in range(R):
+        ref = oracle.measure(s.get_angles(0, k), L)
+        if prec == "fp64":
+            assert abs(obs[k, 0] - ref[0]) <= 1e-9 * N
+            assert abs(obs[k, 2] - ref[2]) <= 1e-12
+        else:
+            assert abs(obs[k, 0] - ref[0]) <= 1e-6 * N
+            assert abs(obs[k, 2] - ref[2]) <= 1e-6
+        assert obs[k, 1] == pytest.approx(obs[k, 0] / N, rel=1e-15)
+        assert obs[k, 3] == pytest.approx(obs[k, 2] ** 2, rel=1e-14)
+        assert obs[k, 4] == pytest.approx(obs[k, 2] ** 4, rel=1e-13)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_measure_special_states(gpu, prec):
+    L = 8
+    N = L ** 3
+    s = make(L, [0.1, 0.2], 3, prec)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    wave = (2 * np.pi * (1 * x + 2 * y + 3 * z) / L).ravel()
+    s.set_angles(np.full(N, 1.0), 0, 0)
+    s.set_angles(wave, 0, 1)
+    obs = s.measure()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert obs[0, 0] == pytest.approx(-3 * N, abs=tol * N)
+    assert obs[0, 2] == pytest.approx(1.0, abs=tol)
+    a = 2 * np.pi * np.array([1, 2, 3]) / L
+    assert obs[1, 0] == pytest.approx(-N * np.cos(a).sum(), abs=tol * N)
+    assert obs[1, 2] == pytest.approx(0.0, abs=tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exchange_matches_oracle(gpu, prec):
+    """Eq. (3) decisions and the resulting permutation, over many steps."""
+    L = 6
+    betas = list(np.linspace(0.3, 0.6, 6))
+    seed = 99
+    s = make(L, betas, seed, prec)
+    perm_ref = list(range(len(betas)))
+    for step in range(12):
+        s.sweep(1, 1)
+        obs = s.measure()
+        E = obs[:, 0].copy()
+        tau = s.counters()[1]
+        key = P.key_of(seed)
+        Ec = E.copy()
+        for k in range(tau % 2, len(betas) - 1, 2):
+            delta = (betas[k] - betas[k + 1]) * (Ec[k] - Ec[k + 1])
+            u = P.uniform(P.philox4x32_10(P.counter(k, tau, 0, 0, P.PHASE_EXCH, 0), key)[0])
+            if abs(u - np.exp(delta)) < 1e-9:
+                pytest.skip("decision within 1e-9 of the threshold")
+        # the oracle's exchange on the measured energies
+        theta = gpu_states(s)
+        oracle.exchange(theta, Ec, L, np.array(betas), seed, tau, 0)
+        s.exchange()
+        after = gpu_states(s)
+        assert np.array_equal(after, theta)
+    assert sorted(s.permutation()) == list(range(len(betas)))
+
+
+def test_exchange_counts_and_bijection(gpu):
+    betas = list(np.linspace(0.44, 0.46, 8))
+    s = make(8, betas, 4, "fp32")
+    for _ in range(20):
+        s.sweep(1, 2)
+        s.measure()
+        acc = s.exchange(with_counts=True)
+    perm = s.permutation()
+    assert sorted(perm) == list(range(8))
+    assert acc[-1] == 0 and acc.sum() > 0
