@@ -67,6 +67,7 @@ struct xy_ctx_s {
     std::vector<LatDev> lat_meas;    // standalone measurement item space
     int items_sweep = 0, items_meas = 0;
     int spt = 0;
+    int halo = 1;          // halo entries per thread of the tiled kernel (1 or 4)
     size_t lds_bytes = 0;
     int grid_sweep = 0;
     size_t partials_cap = 0;
@@ -184,7 +185,7 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
         a.lats = meas_item_space ? c->d_lat_meas : c->d_lat_sweep;
         a.total_items = meas_item_space ? c->items_meas : c->items_sweep;
         const int grid = std::min(a.total_items, c->grid_sweep > 0 ? c->grid_sweep : a.total_items);
-        e = launch_tile_f32(kind, fuse_measure, c->spt, grid, c->lds_bytes, a, c->stream);
+        e = launch_tile_f32(kind, fuse_measure, c->spt, c->halo, grid, c->lds_bytes, a, c->stream);
         if (e == hipSuccess && kind == kMetro && a.recheck)
             e = launch_recheck(c->d_lat_sweep, c->ang, c->d_beta, c->d_pos, colour, c->d_rq, c->d_macc,
                                c->stream);
@@ -332,6 +333,7 @@ void build_layout(xy_ctx c)
     int64_t base = 0;
     int pos_base = 0, item_s = 0, item_m = 0;
     c->spt = 1;
+    c->halo = 1;
     int max_rowbuf = 0;
     c->lat_sweep.clear();
     c->lat_meas.clear();
@@ -353,6 +355,7 @@ void build_layout(xy_ctx c)
             d.nz = d.L / t.TZ;
             d.items_per_slot = d.ny * d.nz;
             c->spt = std::max(c->spt, t.spt);
+            if (d.L > kBlock) c->halo = 4;
             max_rowbuf = std::max(max_rowbuf, (t.TY + 2) * d.half);
         } else {
             d.TY = d.TZ = d.ny = d.nz = 0;

@@ -69,8 +69,8 @@ struct SweepArgs {
 };
 
 // Launchers (stream-ordered, no synchronisation).
-hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int grid, size_t lds_bytes,
-                           const SweepArgs &a, hipStream_t s);
+hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid,
+                           size_t lds_bytes, const SweepArgs &a, hipStream_t s);
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
                           int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);

@@ -15,7 +15,6 @@
 
 namespace xy {
 
-constexpr int kHaloMax = 4;  // halo entries per thread: 2*(L/2) <= 4*kBlock, i.e. L <= 1024
 
 // ---------------------------------------------------------------------------
 // Reductions
@@ -79,11 +78,73 @@ __device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned
     __syncthreads();
 }
 
+// Values that are the same in every lane, moved to scalar registers (loads
+// through kernel-argument pointers otherwise land in vector registers, and
+// buffer descriptors built from them would need per-lane loops).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ LatDev load_lat_uniform(const LatDev *p)
+{
+    LatDev d = *p;
+    d.L = uni(d.L);
+    d.half = uni(d.half);
+    d.R = uni(d.R);
+    d.lat = uni(d.lat);
+    d.base = uni64(d.base);
+    d.N = uni64(d.N);
+    d.pos_base = uni(d.pos_base);
+    d.TY = uni(d.TY);
+    d.TZ = uni(d.TZ);
+    d.ny = uni(d.ny);
+    d.nz = uni(d.nz);
+    d.item_base = uni(d.item_base);
+    d.items_per_slot = uni(d.items_per_slot);
+    return d;
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also fences
+// global memory, which on gfx9 waits for every outstanding global load and
+// store (one shared counter) and would drain the z-plane prefetch at each
+// plane.  The half-sweep kernels exchange data between lanes through LDS
+// only, so an LDS-scoped release/acquire around s_barrier is sufficient.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int find_lattice(const LatDev *lats, int n_lat, int item)
 {
     int li = 0;
     while (li + 1 < n_lat && item >= lats[li + 1].item_base) ++li;
     return li;
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access to one colour array of one slot: a scalar base and byte
+// size, a per-lane byte offset (constant over z) and a scalar byte offset
+// for the plane.  Out-of-range accesses read 0 / are dropped by hardware.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t colour_rsrc(const float *base, int64_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * 4), 0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -93,14 +154,17 @@ __device__ __forceinline__ int find_lattice(const LatDev *lats, int n_lat, int i
 // per plane, turned into (cos, sin) once, kept in registers for the z
 // neighbours (planes z-1, z+1 of the same column) and staged in LDS (plane
 // z plus one halo row above and below the tile, double-buffered) for the
-// x and y neighbours.
+// x and y neighbours.  The loop body is straight-line: lanes past the end of
+// the tile shadow column 0 (same loads, same values) and only their stores
+// are masked, so the next plane's loads stay in flight while this plane is
+// computed.
 //
 // KIND = kMetro / kOver updates colour a.colour; kMeas (colour 1) only
 // measures.  MEAS accumulates E = -sum_{i in colour 1} S_i . h_i (every
 // bond has exactly one colour-1 end) and M = sum over both colours into the
-// item's partials.
+// item's partials.  HALO = halo entries per thread (2*(L/2) <= HALO*kBlock).
 // ---------------------------------------------------------------------------
-template <int KIND, bool MEAS, int SPT>
+template <int KIND, bool MEAS, int SPT, int HALO>
 __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 {
     extern __shared__ f2 lds[];
@@ -108,20 +172,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
     const uint32_t t_sweep = a.ctl->t;
 
     for (int w = blockIdx.x; w < a.total_items; w += gridDim.x) {
-        const int li = find_lattice(a.lats, a.n_lat, w);
-        const LatDev d = a.lats[li];
+        const int li = uni(find_lattice(a.lats, a.n_lat, w));
+        const LatDev d = load_lat_uniform(a.lats + li);
         const int L = d.L, half = d.half, TY = d.TY;
         const int wl = w - d.item_base;
         const int slot = wl / d.items_per_slot;
         const int rem = wl - slot * d.items_per_slot;
         const int ty = rem % d.ny, tz = rem / d.ny;
         const int y0 = ty * TY, z0 = tz * d.TZ;
-        const int k = a.pos[d.pos_base + slot];
-        const float beta = (float)a.beta[d.pos_base + k];
-        const int64_t plane = (int64_t)L * half;
-        float *angs = (float *)a.ang + d.base + (int64_t)slot * d.N;
-        float *own = angs + (int64_t)a.colour * (d.N / 2);
-        const float *oth = angs + (int64_t)(a.colour ^ 1) * (d.N / 2);
+        const int k = uni(a.pos[d.pos_base + slot]);
+        const float beta = __builtin_bit_cast(float, uni(__builtin_bit_cast(int, (float)a.beta[d.pos_base + k])));
+        const uint32_t plane_b = (uint32_t)L * (uint32_t)half * 4u;  // bytes per plane
+        const float *angs = (const float *)a.ang + d.base + (int64_t)slot * d.N;
+        const __amdgpu_buffer_rsrc_t rown = colour_rsrc(angs + (int64_t)a.colour * (d.N / 2), d.N / 2);
+        const __amdgpu_buffer_rsrc_t roth = colour_rsrc(angs + (int64_t)(a.colour ^ 1) * (d.N / 2), d.N / 2);
         const int nsite = TY * half;
         f2 *buf0 = lds;
         f2 *buf1 = lds + (TY + 2) * half;
@@ -129,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         const uint32_t c2 = ((uint32_t)d.lat << 16) | (uint32_t)k;
         const uint32_t c3 = (kPhaseMetro << 24) | (uint32_t)a.substep;
 
-        int off[SPT], lc[SPT], lxm[SPT], lxp[SPT], ypar[SPT];
-        uint32_t ibase[SPT];
+        uint32_t voff[SPT], ibase[SPT];
+        int lc[SPT], lxm[SPT], lxp[SPT], ypar[SPT];
         bool ok[SPT];
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
@@ -140,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
             const int yl = fl / half;
             const int j = fl - yl * half;
             const int y = y0 + yl;
-            off[s] = y * half + j;
+            voff[s] = (uint32_t)(y * half + j) * 4u;
             lc[s] = (yl + 1) * half + j;
             lxm[s] = (yl + 1) * half + ((j == 0) ? half - 1 : j - 1);
             lxp[s] = (yl + 1) * half + ((j + 1 == half) ? 0 : j + 1);
@@ -149,86 +213,89 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         }
         const int ym = (y0 == 0) ? L - 1 : y0 - 1;
         const int yp = (y0 + TY == L) ? 0 : y0 + TY;
-        int hoff[kHaloMax], hl[kHaloMax];
-        bool hok[kHaloMax];
+        uint32_t hvoff[HALO];
+        int hl[HALO];
+        bool hok[HALO];
 #pragma unroll
-        for (int h = 0; h < kHaloMax; ++h) {
+        for (int h = 0; h < HALO; ++h) {
             const int e = tid + h * kBlock;
             hok[h] = e < 2 * half;
             const int ee = hok[h] ? e : 0;
             const int r = ee >= half;
             const int jj = ee - r * half;
-            hoff[h] = (r ? yp : ym) * half + jj;
+            hvoff[h] = (uint32_t)((r ? yp : ym) * half + jj) * 4u;
             hl[h] = (r ? (TY + 1) : 0) * half + jj;
         }
 
-        // prologue: planes z0-1, z0, z0+1 of the other colour, plane z0 of ours
+        // Prologue.  Converted: other colour at z0-1, z0, z0+1; raw (in flight
+        // one plane ahead of use): other colour at z0+2, ours at z0+1, halo
+        // at z0+1.  Plane z0 of the other colour (tile and halo) goes to LDS.
+        auto wrapz = [L](int z) { return z >= L ? z - L : z; };
         const int zm1 = (z0 == 0) ? L - 1 : z0 - 1;
-        const int zp1 = (z0 + 1 == L) ? 0 : z0 + 1;
         f2 ocm[SPT], oc0[SPT], ocp[SPT];
         float cur[SPT];
+        float a_o[SPT], a_c[SPT], a_h[HALO], b_o[SPT], b_c[SPT], b_h[HALO];
+        int lx_even[SPT], lx_odd[SPT];  // LDS index of the x-neighbour on even / odd steps
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
-            float am = 0.f, a0 = 0.f, ap = 0.f, ac = 0.f;
-            if (ok[s]) {
-                am = oth[(int64_t)zm1 * plane + off[s]];
-                a0 = oth[(int64_t)z0 * plane + off[s]];
-                ap = oth[(int64_t)zp1 * plane + off[s]];
-                ac = own[(int64_t)z0 * plane + off[s]];
-            }
-            ocm[s] = sincos_turns(am);
-            oc0[s] = sincos_turns(a0);
-            ocp[s] = sincos_turns(ap);
-            cur[s] = ac;
-            if (ok[s]) buf0[lc[s]] = oc0[s];
+            const bool p_even = ((ypar[s] + z0) & 1) != 0;
+            lx_even[s] = p_even ? lxp[s] : lxm[s];
+            lx_odd[s] = p_even ? lxm[s] : lxp[s];
+            ocm[s] = sincos_turns(bload(roth, voff[s], (uint32_t)zm1 * plane_b));
+            oc0[s] = sincos_turns(bload(roth, voff[s], (uint32_t)z0 * plane_b));
+            ocp[s] = sincos_turns(bload(roth, voff[s], (uint32_t)wrapz(z0 + 1) * plane_b));
+            cur[s] = bload(rown, voff[s], (uint32_t)z0 * plane_b);
+            a_o[s] = bload(roth, voff[s], (uint32_t)wrapz(z0 + 2) * plane_b);
+            a_c[s] = bload(rown, voff[s], (uint32_t)wrapz(z0 + 1) * plane_b);
+            buf0[lc[s]] = oc0[s];
         }
 #pragma unroll
-        for (int h = 0; h < kHaloMax; ++h)
-            if (hok[h]) buf0[hl[h]] = sincos_turns(oth[(int64_t)z0 * plane + hoff[h]]);
-        __syncthreads();
+        for (int h = 0; h < HALO; ++h) {
+            const f2 v = sincos_turns(bload(roth, hvoff[h], (uint32_t)z0 * plane_b));
+            if (hok[h]) buf0[hl[h]] = v;
+            a_h[h] = bload(roth, hvoff[h], (uint32_t)wrapz(z0 + 1) * plane_b);
+        }
+        lds_barrier();
 
         double accE = 0.0, accX = 0.0, accY = 0.0;
         unsigned long long nacc = 0;
 
-        for (int zz = 0; zz < d.TZ; ++zz) {
+        // One plane.  pre_* were loaded one step ago and are consumed at the
+        // end of this step; nxt_* are issued now and consumed next step.  The
+        // loop below alternates the two register sets (and the two LDS
+        // buffers) so that no in-flight load is ever copied between registers,
+        // which would force the wait early.
+        auto step = [&](const int zz, const f2 *bc, f2 *bn, const int (&lx)[SPT], float (&pre_o)[SPT],
+                        float (&pre_c)[SPT], float (&pre_h)[HALO], float (&nxt_o)[SPT],
+                        float (&nxt_c)[SPT], float (&nxt_h)[HALO]) {
             const int z = z0 + zz;
-            const int zn = (z + 1 == L) ? 0 : z + 1;
-            const int zn2 = (zn + 1 == L) ? 0 : zn + 1;
-            const f2 *bc = (zz & 1) ? buf1 : buf0;
-            f2 *bn = (zz & 1) ? buf0 : buf1;
-            const bool more = zz + 1 < d.TZ;
-
-            float rawo[SPT], rawc[SPT], rawh[kHaloMax];
+            const uint32_t sz = (uint32_t)z * plane_b;
+            {
+                const uint32_t s3 = (uint32_t)wrapz(wrapz(z + 1) + 2) * plane_b;
+                const uint32_t s2 = (uint32_t)wrapz(wrapz(z + 1) + 1) * plane_b;
 #pragma unroll
-            for (int s = 0; s < SPT; ++s) {
-                rawo[s] = 0.f;
-                rawc[s] = 0.f;
-                if (more && ok[s]) {
-                    rawo[s] = oth[(int64_t)zn2 * plane + off[s]];
-                    rawc[s] = own[(int64_t)zn * plane + off[s]];
+                for (int s = 0; s < SPT; ++s) {
+                    nxt_o[s] = bload(roth, voff[s], s3);
+                    nxt_c[s] = bload(rown, voff[s], s2);
                 }
-            }
 #pragma unroll
-            for (int h = 0; h < kHaloMax; ++h) {
-                rawh[h] = 0.f;
-                if (more && hok[h]) rawh[h] = oth[(int64_t)zn * plane + hoff[h]];
+                for (int h = 0; h < HALO; ++h) nxt_h[h] = bload(roth, hvoff[h], s2);
             }
 
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
-                if (!ok[s]) continue;
-                const int p = (ypar[s] + z) & 1;
                 const f2 n1 = bc[lc[s] - half];
                 const f2 n2 = bc[lc[s] + half];
                 const f2 n3 = bc[lc[s]];
-                const f2 n4 = bc[p ? lxp[s] : lxm[s]];
+                const f2 n4 = bc[lx[s]];
                 const float hx = ((ocm[s].c + ocp[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
                 const float hy = ((ocm[s].s + ocp[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
                 float nv = cur[s];
                 if constexpr (KIND == kOver) {
                     nv = overrelax_turns(cur[s], hx, hy);
                 } else if constexpr (KIND == kMetro) {
-                    const uint32_t i = ibase[s] + (uint32_t)p + LL * (uint32_t)z;
+                    const uint32_t p = (uint32_t)((ypar[s] + z) & 1);
+                    const uint32_t i = ibase[s] + p + LL * (uint32_t)z;
                     const u32x4 r = philox4x32_10(i, t_sweep, c2, c3, a.k0, a.k1);
                     const float u0 = unit24f(r.x), u1 = unit24f(r.y);
                     const f2 so = sincos_turns(cur[s]);
@@ -236,13 +303,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
                     const float pa = __expf(-beta * dE);
                     const bool acc = u1 < pa;
-                    if (a.recheck && __builtin_fabsf(u1 - pa) < 1e-5f) {
+                    if (a.recheck && __builtin_fabsf(u1 - pa) < 1e-5f && ok[s]) {
                         const uint32_t idx = atomicAdd(&a.rq->count, 1u);
                         if (idx < a.rq->capacity) {
                             RecheckEntry e;
                             e.li = li;
                             e.slot = slot;
-                            e.q = (int32_t)((int64_t)z * plane + off[s]);
+                            e.q = (int32_t)((sz + voff[s]) >> 2);
                             e.cur = cur[s];
                             e.u0 = u0;
                             e.u1 = u1;
@@ -254,31 +321,41 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                         }
                     }
                     nv = acc ? u0 : cur[s];
-                    nacc += acc ? 1ull : 0ull;
+                    nacc += (acc && ok[s]) ? 1ull : 0ull;
                 }
                 if constexpr (MEAS || KIND == kMeas) {
-                    const f2 sc = sincos_turns(nv);
-                    accE -= (double)sc.c * (double)hx + (double)sc.s * (double)hy;
-                    accX += (double)sc.c + (double)oc0[s].c;
-                    accY += (double)sc.s + (double)oc0[s].s;
+                    if (ok[s]) {
+                        const f2 sc = sincos_turns(nv);
+                        accE -= (double)sc.c * (double)hx + (double)sc.s * (double)hy;
+                        accX += (double)sc.c + (double)oc0[s].c;
+                        accY += (double)sc.s + (double)oc0[s].s;
+                    }
                 }
-                if constexpr (KIND != kMeas) own[(int64_t)z * plane + off[s]] = nv;
+                if constexpr (KIND != kMeas) {
+                    if (ok[s]) bstore(nv, rown, voff[s], sz);
+                }
             }
 
-            if (more) {
+            // Plane z+1 into the other LDS buffer and rotate the z window.
 #pragma unroll
-                for (int s = 0; s < SPT; ++s) {
-                    if (ok[s]) bn[lc[s]] = ocp[s];
-                    ocm[s] = oc0[s];
-                    oc0[s] = ocp[s];
-                    ocp[s] = sincos_turns(rawo[s]);
-                    cur[s] = rawc[s];
-                }
-#pragma unroll
-                for (int h = 0; h < kHaloMax; ++h)
-                    if (hok[h]) bn[hl[h]] = sincos_turns(rawh[h]);
+            for (int s = 0; s < SPT; ++s) {
+                bn[lc[s]] = ocp[s];
+                ocm[s] = oc0[s];
+                oc0[s] = ocp[s];
+                ocp[s] = sincos_turns(pre_o[s]);
+                cur[s] = pre_c[s];
             }
-            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < HALO; ++h) {
+                const f2 v = sincos_turns(pre_h[h]);
+                if (hok[h]) bn[hl[h]] = v;
+            }
+            lds_barrier();
+        };
+
+        for (int zz = 0; zz < d.TZ; zz += 2) {
+            step(zz, buf0, buf1, lx_even, a_o, a_c, a_h, b_o, b_c, b_h);
+            if (zz + 1 < d.TZ) step(zz + 1, buf1, buf0, lx_odd, b_o, b_c, b_h, a_o, a_c, a_h);
         }
 
         if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
@@ -480,28 +557,36 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
     const LatDev d = lats[blockIdx.x];
     const int pb = d.pos_base;
     if (do_sum) {
+        // one wavefront per slot: lanes stride over the slot's items, then a
+        // fixed butterfly; the order depends only on the item layout
         double *out = obs;
         if (out && use_ring) out += (int64_t)ctl->ring * ring_stride;
-        for (int r = threadIdx.x; r < d.R; r += blockDim.x) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int r = wv; r < d.R; r += nw) {
             const double *pp = partials + 3 * ((int64_t)d.item_base + (int64_t)r * d.items_per_slot);
             double E = 0.0, mx = 0.0, my = 0.0;
-            for (int it = 0; it < d.items_per_slot; ++it) {
+            for (int it = lane; it < d.items_per_slot; it += 64) {
                 E += pp[3 * it + 0];
                 mx += pp[3 * it + 1];
                 my += pp[3 * it + 2];
             }
-            E_slot[pb + r] = E;
-            if (!isfinite(E) || !isfinite(mx) || !isfinite(my)) atomicOr(bad, 1);
-            if (out) {
-                const int kk = pos[pb + r];
-                const double n = (double)d.N;
-                const double m = sqrt(mx * mx + my * my) / n;
-                double *o = out + 5 * (int64_t)(pb + kk);
-                o[0] = E;
-                o[1] = E / n;
-                o[2] = m;
-                o[3] = m * m;
-                o[4] = (m * m) * (m * m);
+            E = wave_sum(E);
+            mx = wave_sum(mx);
+            my = wave_sum(my);
+            if (lane == 0) {
+                E_slot[pb + r] = E;
+                if (!isfinite(E) || !isfinite(mx) || !isfinite(my)) atomicOr(bad, 1);
+                if (out) {
+                    const int kk = pos[pb + r];
+                    const double n = (double)d.N;
+                    const double m = sqrt(mx * mx + my * my) / n;
+                    double *o = out + 5 * (int64_t)(pb + kk);
+                    o[0] = E;
+                    o[1] = E / n;
+                    o[2] = m;
+                    o[3] = m * m;
+                    o[4] = (m * m) * (m * m);
+                }
             }
         }
         __syncthreads();
@@ -539,32 +624,41 @@ __global__ void k_tick(Ctl *ctl, uint32_t dt, uint32_t dtau, uint32_t dring, int
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int KIND, bool MEAS>
+template <int KIND, bool MEAS, int HALO>
 static hipError_t launch_tile_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s)
 {
     switch (spt) {
-    case 1: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 1>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 2>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 3>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 4>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 5>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 6: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 6>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 8>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 1, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 2, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 3, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 4, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 5, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 6: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 6, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 8, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int grid, size_t lds,
-                           const SweepArgs &a, hipStream_t s)
+template <int HALO>
+static hipError_t launch_tile_halo(int kind, bool fuse_measure, int spt, int grid, size_t lds,
+                                   const SweepArgs &a, hipStream_t s)
 {
     if (kind == kMetro)
-        return fuse_measure ? launch_tile_spt<kMetro, true>(spt, grid, lds, a, s)
-                            : launch_tile_spt<kMetro, false>(spt, grid, lds, a, s);
+        return fuse_measure ? launch_tile_spt<kMetro, true, HALO>(spt, grid, lds, a, s)
+                            : launch_tile_spt<kMetro, false, HALO>(spt, grid, lds, a, s);
     if (kind == kOver)
-        return fuse_measure ? launch_tile_spt<kOver, true>(spt, grid, lds, a, s)
-                            : launch_tile_spt<kOver, false>(spt, grid, lds, a, s);
-    return launch_tile_spt<kMeas, false>(spt, grid, lds, a, s);
+        return fuse_measure ? launch_tile_spt<kOver, true, HALO>(spt, grid, lds, a, s)
+                            : launch_tile_spt<kOver, false, HALO>(spt, grid, lds, a, s);
+    return launch_tile_spt<kMeas, false, HALO>(spt, grid, lds, a, s);
+}
+
+hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid, size_t lds,
+                           const SweepArgs &a, hipStream_t s)
+{
+    if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, spt, grid, lds, a, s);
+    if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, spt, grid, lds, a, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
@@ -607,7 +701,7 @@ hipError_t launch_finalize(const LatDev *lats, int n_lat, int max_R, const doubl
                            uint32_t k1, int *bad, hipStream_t s)
 {
     int threads = 64;
-    while (threads < max_R && threads < 1024) threads *= 2;
+    while (threads < 64 * max_R && threads < 1024) threads *= 2;
     hipLaunchKernelGGL(k_finalize, dim3(n_lat), dim3(threads), 0, s, lats, partials, beta, pos,
                        slot_of, E_slot, obs, use_ring, ring_stride, do_sum, do_exchange, sacc, ctl,
                        k0, k1, bad);
