@@ -34,6 +34,7 @@ BYTES_PER_UPDATE_F64 = 24.0
 L, R, SEED = 160, 32, 4
 BETA_LO, BETA_HI = 0.4538, 0.4546
 N_METRO, N_OR = 1, 10
+DEFAULT_TILING = "8x20"
 
 
 def _oracle_one_sweep(args):
@@ -96,6 +97,59 @@ def load_traffic(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30
+
+
+def traffic_probe(sim, dev):
+    """Workload for `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`: a plain
+    device copy of COPY_BYTES (the calibration kernel: it must read and write
+    exactly that many bytes), then one over-relaxation substep (two half-sweep
+    launches) of the bench configuration."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    sim.sweep(0, 1)
+    torch.cuda.synchronize()
+    print("[bench] traffic probe done", file=sys.stderr, flush=True)
+
+
+def _pmc_rows(path, counter):
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r.get("Kernel_Name", "")
+            if r.get("Counter_Name") == counter:
+                rows.append((name, float(r["Counter_Value"])))
+    return rows
+
+
+def digest_traffic(fetch_csv, write_csv):
+    """Scale the over-relaxation kernel's FETCH_SIZE / WRITE_SIZE by what the
+    same counters read for the plain copy of COPY_BYTES, and store the HBM
+    bytes per launch together with the kernel source hash."""
+    out = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _pmc_rows(path, counter)
+        copy = [v for n, v in rows if "elementwise" in n or "copy" in n.lower()]
+        over = [v for n, v in rows if "k_tile_f32" in n and ("ILi1E" in n or "<1," in n or "(xy::Kind)1" in n)]
+        if not copy or not over:
+            raise SystemExit(f"{path}: copy or over-relaxation dispatches not found")
+        scale = COPY_BYTES / max(copy)
+        out[f"{key}_counter_per_launch"] = sum(over) / len(over)
+        out[f"{key}_copy_counter"] = max(copy)
+        out[f"{key}_scale_bytes_per_unit"] = scale
+        out[f"{key}_bytes_per_launch"] = out[f"{key}_counter_per_launch"] * scale
+    out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    out["algorithmic_bytes_per_launch"] = BYTES_PER_UPDATE_F32 * R * L ** 3 / 2
+    path = os.path.join(ROOT, "profiles", "traffic_over_relax_L160x32.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +158,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="extra eagerly launched sweeps timed per kernel with HIP events")
+    ap.add_argument("--tiling", default=DEFAULT_TILING,
+                    help="'TYxTZ' for the tiled half-sweep, or 'auto' to run the autotuner "
+                         f"(default {DEFAULT_TILING}: the autotuner's pick for this workload, fixed "
+                         "so that timing and counter runs use the same launch shape)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only the workload for HBM counter collection: a plain 1 GiB device "
+                         "copy, then one over-relaxation substep of the bench configuration")
+    ap.add_argument("--digest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs of --traffic-probe into "
+                         "profiles/traffic_over_relax_L160x32.json")
     args = ap.parse_args()
+    if args.digest_traffic:
+        digest_traffic(*args.digest_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "shards by replica across GPUs but no multi-GPU path is built", file=sys.stderr)
@@ -119,6 +186,16 @@ def main():
     betas = np.linspace(BETA_LO, BETA_HI, R)
     sim = Sim(L, [betas], seed=SEED, prec="fp32")
     N = L ** 3
+    if args.tiling == "auto":
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        tiling = sim.autotune(N_METRO, N_OR, reps=3)[0]
+    else:
+        ty, tz = (int(v) for v in args.tiling.split("x"))
+        sim.set_tiling(0, ty, tz, 0)
+        tiling = sim.get_tiling(0)
+    if args.traffic_probe:
+        traffic_probe(sim, dev)
+        return
     obs = torch.zeros((max(args.steps, args.warmup, 1), R, 5), dtype=torch.float64, device=dev)
 
     print(f"[bench] warmup {args.warmup} sweeps", file=sys.stderr, flush=True)
@@ -216,6 +293,7 @@ def main():
                         "over-relaxation, measurement and exchange every sweep, random start",
             "L": L, "replicas": R, "n_metro": N_METRO, "n_or": N_OR, "seed": SEED,
             "site_updates_per_step": (N_METRO + N_OR) * N * R,
+            "tiling": {"ty": tiling[0], "tz": tiling[1], "grid_cap": tiling[2]},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -81,7 +81,6 @@ typedef enum {
 
 /* xy_config.flags */
 #define XY_F_NO_RECHECK  0x1u /* FP32: take Metropolis decisions in float32 only */
-#define XY_F_NO_AUTOTUNE 0x2u /* use the built-in tile choice instead of timing candidates */
 
 typedef struct {
     int32_t n_lattices;          /* >= 1 */
@@ -176,9 +175,34 @@ xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
 xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *ms,
                             int32_t *launches);
 
+/*
+ * xy_run that also records, per sweep, the bond sums behind the spin
+ * stiffness of Eq. (6) into bonds_dev (device, n_sweeps*6*R_total doubles,
+ * sweep s at offset 6*R_total*s, position p at 6*p): {C_x, C_y, C_z, I_x,
+ * I_y, I_z} with C_mu = sum_i cos(theta_i - theta_{i+mu}) and
+ * I_mu = sum_i sin(theta_i - theta_{i+mu}), each bond (i, i+mu) once, in
+ * float64.  Then rho_s = (1/3N) sum_mu [<C_mu> - beta <I_mu^2>].
+ * Either ring may be NULL.  Asynchronous.
+ */
+xy_status xy_run_ex(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
+                    int32_t exchange_every, double *obs_dev, double *bonds_dev);
+
+/* The bond sums {C_x, C_y, C_z, I_x, I_y, I_z} (see xy_run_ex) of every
+ * configuration in its current state, by position index (6*R_total
+ * doubles); device or host destination as for xy_measure.  Measures first
+ * when the state changed since the last measurement. */
+xy_status xy_get_bond_sums(xy_ctx ctx, double *out, int32_t out_on_device);
+
 /* Copy the N_l angles (radians in [0, 2pi), natural site order) of the
  * configuration at (lattice, beta_pos) to host memory.  Waits. */
 xy_status xy_get_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *host);
+
+/* The angles (radians) of n chosen sites (natural index i = x + L*(y + L*z),
+ * 0 <= i < N_l) of the configuration at (lattice, beta_pos), in order, into
+ * host memory; n <= 2^26.  For sampled checks of lattices too large to copy
+ * whole.  Waits. */
+xy_status xy_get_sites(xy_ctx ctx, int32_t lattice, int32_t beta_pos, int64_t n,
+                       const int64_t *sites, double *host);
 
 /* Overwrite that configuration from host radians (any finite values; they are
  * wrapped into [0, 2pi) and, for FP32, rounded to float32 turns).  Waits. */
@@ -204,6 +228,17 @@ xy_status xy_get_metro_accepts(xy_ctx ctx, int64_t *n_acc);
  * XY_ERR_UNSUPPORTED for FP64 contexts.  Takes effect for later calls.
  */
 xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap);
+
+/*
+ * Pick (ty, tz) per lattice by timing: for every admissible tiling, reps
+ * launches of one Metropolis and one over-relaxation half-sweep of that
+ * lattice alone, cost = n_metro * t_metro + n_or * t_over; the cheapest is
+ * kept.  The lattice's angles and acceptance counters are saved and restored
+ * around the timing (the chain is unchanged), and near-threshold float64
+ * re-decisions are off while timing.  Needs scratch device memory the size
+ * of the largest lattice's angles.  No-op for FP64 contexts.  Waits.
+ */
+xy_status xy_autotune(xy_ctx ctx, int32_t n_metro, int32_t n_or, int32_t reps);
 xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
 
 /*

@@ -55,6 +55,10 @@ def lib():
         L.orc_init.restype = None
         L.orc_metro_half.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_int]
         L.orc_metro_half.restype = ctypes.c_int64
+        L.orc_metro_site.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, ctypes.c_int64]
+        L.orc_metro_site.restype = c_int
+        L.orc_or_site.argtypes = [dp, c_int, ctypes.c_int64]
+        L.orc_or_site.restype = None
         L.orc_or_half.argtypes = [dp, c_int, c_int]
         L.orc_or_half.restype = None
         L.orc_sweep.argtypes = [dp, c_int, c_int, dp, c_u64, c_u32, c_int, c_int, c_int, i64p]
@@ -108,6 +112,18 @@ def metro_half(theta, L, beta, seed, t, lat, k, substep, colour):
     """In place on one configuration (float64 array of N).  Returns accepts."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
     return lib().orc_metro_half(_dp(theta), L, float(beta), seed, t, lat, k, substep, colour)
+
+
+def metro_site(theta, L, beta, seed, t, lat, k, substep, i):
+    """Metropolis update of site i alone (in place); returns 1 if accepted."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
+    return lib().orc_metro_site(_dp(theta), L, float(beta), seed, t, lat, k, substep, int(i))
+
+
+def or_site(theta, L, i):
+    """Over-relaxation of site i alone (in place)."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
+    lib().orc_or_site(_dp(theta), L, int(i))
 
 
 def or_half(theta, L, colour):

@@ -117,17 +117,40 @@ void orc_init(double *theta, int L, int R, int lat, uint64_t seed)
 }
 
 /* ------------------------------------------------------------------------
- * One Metropolis half-sweep over the sites of one colour (Sec. II:
- * checkerboard decomposition, all black sites, then all white sites).
- *
- * For each site i of that colour, in increasing i, with
+ * Metropolis update of one site i, and the half-sweep over the sites of one
+ * colour (Sec. II: checkerboard decomposition, all black sites, then all
+ * white sites), which applies it to every site of that colour in increasing
+ * i.  With
  * r = Philox(i, t, (lat << 16) | k, (METRO << 24) | substep):
  *     proposal   theta' = 2*pi*U(r0)        (uniform on the circle)
  *     dE         = H(theta') - H(theta), evaluated from Eq. (1) over the six
  *                  bonds of site i:  sum_j [cos(theta - theta_j) - cos(theta' - theta_j)]
  *     accept iff U(r1) < exp(-beta * dE)
- * Returns the number of accepted moves.
+ * The site update returns 1 if accepted; the half-sweep returns the count.
  * ------------------------------------------------------------------------ */
+int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
+                   int k, int substep, int64_t i)
+{
+    int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+    int64_t nb[6];
+    neighbours(L, x, y, z, nb);
+    uint32_t r[4];
+    draw(seed, (uint32_t)i, t, (uint32_t)lat, (uint32_t)k, ORC_PHASE_METRO, (uint32_t)substep, r);
+    double th_old = theta[i];
+    double th_new = TWO_PI * orc_uniform(r[0]);
+    double u = orc_uniform(r[1]);
+    double dE = 0.0;
+    for (int n = 0; n < 6; ++n) {
+        double thj = theta[nb[n]];
+        dE += cos(th_old - thj) - cos(th_new - thj);
+    }
+    if (u < exp(-beta * dE)) {
+        theta[i] = th_new;
+        return 1;
+    }
+    return 0;
+}
+
 int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_t t,
                        int lat, int k, int substep, int colour)
 {
@@ -137,56 +160,46 @@ int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_
             for (int x = 0; x < L; ++x) {
                 if (((x + y + z) & 1) != colour) continue;
                 int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
-                int64_t nb[6];
-                neighbours(L, x, y, z, nb);
-                uint32_t r[4];
-                draw(seed, (uint32_t)i, t, (uint32_t)lat, (uint32_t)k, ORC_PHASE_METRO,
-                     (uint32_t)substep, r);
-                double th_old = theta[i];
-                double th_new = TWO_PI * orc_uniform(r[0]);
-                double u = orc_uniform(r[1]);
-                double dE = 0.0;
-                for (int n = 0; n < 6; ++n) {
-                    double thj = theta[nb[n]];
-                    dE += cos(th_old - thj) - cos(th_new - thj);
-                }
-                if (u < exp(-beta * dE)) {
-                    theta[i] = th_new;
-                    ++accepted;
-                }
+                accepted += orc_metro_site(theta, L, beta, seed, t, lat, k, substep, i);
             }
     return accepted;
 }
 
 /* ------------------------------------------------------------------------
- * One over-relaxation half-sweep over the sites of one colour, Eq. (2):
+ * Over-relaxation of one site i, and the half-sweep applying it to every
+ * site of one colour, Eq. (2):
  *     H_i  = - sum_j S_j                      (local molecular field)
  *     S_i' = - S_i + 2 (S_i . H_i / H_i^2) H_i
  * with S = (cos theta, sin theta); the new angle is the polar angle of S_i'.
  * Where H_i is exactly zero the reflection is undefined and the spin is left
  * unchanged.
  * ------------------------------------------------------------------------ */
+void orc_or_site(double *theta, int L, int64_t i)
+{
+    int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+    int64_t nb[6];
+    neighbours(L, x, y, z, nb);
+    double Hx = 0.0, Hy = 0.0;
+    for (int n = 0; n < 6; ++n) {
+        Hx -= cos(theta[nb[n]]);
+        Hy -= sin(theta[nb[n]]);
+    }
+    double H2 = Hx * Hx + Hy * Hy;
+    if (H2 == 0.0) return;
+    double Sx = cos(theta[i]), Sy = sin(theta[i]);
+    double f = 2.0 * (Sx * Hx + Sy * Hy) / H2;
+    double Sx_new = -Sx + f * Hx;
+    double Sy_new = -Sy + f * Hy;
+    theta[i] = wrap_angle(atan2(Sy_new, Sx_new));
+}
+
 void orc_or_half(double *theta, int L, int colour)
 {
     for (int z = 0; z < L; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
                 if (((x + y + z) & 1) != colour) continue;
-                int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
-                int64_t nb[6];
-                neighbours(L, x, y, z, nb);
-                double Hx = 0.0, Hy = 0.0;
-                for (int n = 0; n < 6; ++n) {
-                    Hx -= cos(theta[nb[n]]);
-                    Hy -= sin(theta[nb[n]]);
-                }
-                double H2 = Hx * Hx + Hy * Hy;
-                if (H2 == 0.0) continue;
-                double Sx = cos(theta[i]), Sy = sin(theta[i]);
-                double f = 2.0 * (Sx * Hx + Sy * Hy) / H2;
-                double Sx_new = -Sx + f * Hx;
-                double Sy_new = -Sy + f * Hy;
-                theta[i] = wrap_angle(atan2(Sy_new, Sx_new));
+                orc_or_site(theta, L, x + (int64_t)L * (y + (int64_t)L * z));
             }
 }
 

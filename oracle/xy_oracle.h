@@ -11,6 +11,9 @@
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_uniform(uint32_t r);
 void orc_init(double *theta, int L, int R, int lat, uint64_t seed);
+int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
+                   int k, int substep, int64_t i);
+void orc_or_site(double *theta, int L, int64_t i);
 int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
                        int k, int substep, int colour);
 void orc_or_half(double *theta, int L, int colour);

@@ -14,7 +14,6 @@ XY_OK, XY_ERR_ARG, XY_ERR_ODD_L, XY_ERR_OOM, XY_ERR_HIP, XY_ERR_STATE, XY_ERR_UN
 XY_FP32, XY_FP64 = 0, 1
 XY_START_RANDOM, XY_START_ORDERED = 0, 1
 XY_F_NO_RECHECK = 0x1
-XY_F_NO_AUTOTUNE = 0x2
 
 STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM", 4: "XY_ERR_HIP",
                 5: "XY_ERR_STATE", 6: "XY_ERR_UNSUPPORTED"}
@@ -22,7 +21,7 @@ STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM",
 EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange", "xy_run",
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
-           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled"]
+           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums"]
 
 
 class XYConfig(ctypes.Structure):
@@ -95,6 +94,14 @@ def lib():
         L.xy_get_tiling.restype = i32
         L.xy_sweep_profiled.argtypes = [vp, i32, i32, dp, ip]
         L.xy_sweep_profiled.restype = i32
+        L.xy_autotune.argtypes = [vp, i32, i32, i32]
+        L.xy_autotune.restype = i32
+        L.xy_get_sites.argtypes = [vp, i32, i32, ctypes.c_int64, i64p, dp]
+        L.xy_get_sites.restype = i32
+        L.xy_run_ex.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+        L.xy_run_ex.restype = i32
+        L.xy_get_bond_sums.argtypes = [vp, vp, i32]
+        L.xy_get_bond_sums.restype = i32
         L.xy_destroy.argtypes = [vp]
         L.xy_destroy.restype = None
         _lib = L

@@ -32,10 +32,11 @@ struct Tiling {
 
 struct GraphKey {
     int n_metro = -1, n_or = -1, exch = -1;
-    double *obs = nullptr;
+    double *obs = nullptr, *bonds = nullptr;
     bool operator==(const GraphKey &o) const
     {
-        return n_metro == o.n_metro && n_or == o.n_or && exch == o.exch && obs == o.obs;
+        return n_metro == o.n_metro && n_or == o.n_or && exch == o.exch && obs == o.obs &&
+               bonds == o.bonds;
     }
 };
 
@@ -82,6 +83,7 @@ struct xy_ctx_s {
     double *d_partials = nullptr;
     double *d_E = nullptr;
     double *d_obs = nullptr;
+    double *d_bonds = nullptr;     // [R_total][6] bond sums of the last eager measurement
     unsigned long long *d_macc = nullptr, *d_sacc = nullptr;
     int *d_bad = nullptr;
     RecheckQueue *d_rq = nullptr;
@@ -91,6 +93,7 @@ struct xy_ctx_s {
     // host mirrors
     uint64_t t = 0, tau = 0;
     bool e_fresh = false;          // d_E matches the current configurations
+    bool bonds_fresh = false;      // d_bonds matches the current configurations
     bool partials_are_sweep = false;
 
     std::vector<GraphEntry> graphs;
@@ -133,26 +136,20 @@ int spt_for(int sites)
     return 8;
 }
 
-// Default tile of the FP32 kernel: the widest y-tile with at most 5 sites per
-// thread, then the deepest z-chunk that still leaves about 1024 work items
-// per lattice so the 256 CUs stay busy.
+// Default tile of the FP32 kernel (xy_autotune refines it by timing): about
+// 2.5 sites per thread in the y-tile (measured on gfx950 at L = 160 to balance
+// occupancy against halo overhead), and z-chunks of at most 24 planes.
 Tiling default_tiling(int L, int R)
 {
+    (void)R;
     const int half = L / 2;
     Tiling t;
     for (int d : divisors(L))
-        if (d * half <= 5 * kBlock) t.TY = d;
+        if (d * half <= 3 * kBlock) t.TY = d;
     if (t.TY == 0) t.TY = 1;
-    const int ny = L / t.TY;
     t.TZ = 1;
-    for (int d : divisors(L)) {
-        const int64_t items = (int64_t)R * ny * (L / d);
-        if (items >= 1024 && d <= 64) t.TZ = d;
-    }
-    if (t.TZ == 1) {
-        for (int d : divisors(L))
-            if (d <= 8) t.TZ = d;
-    }
+    for (int d : divisors(L))
+        if (d <= 24) t.TZ = d;
     t.spt = spt_for(t.TY * half);
     return t;
 }
@@ -230,12 +227,13 @@ const LatDev *meas_layout_dev(xy_ctx c, bool from_sweep)
 }
 
 xy_status enqueue_finalize(xy_ctx c, bool from_sweep_partials, double *obs, int use_ring,
-                           bool do_sum, bool do_exchange)
+                           bool do_sum, bool do_exchange, double *bonds = nullptr)
 {
     XY_HIP(c, launch_finalize(meas_layout_dev(c, from_sweep_partials), c->n_lat, c->max_R,
-                              c->d_partials, c->d_beta, c->d_pos, c->d_slot_of, c->d_E, obs, use_ring,
-                              (int64_t)5 * c->R_total, do_sum ? 1 : 0, do_exchange ? 1 : 0,
-                              c->d_sacc, c->d_ctl, c->k0, c->k1, c->d_bad, c->stream));
+                              c->d_partials, c->d_beta, c->d_pos, c->d_slot_of, c->d_E, obs, bonds,
+                              use_ring, (int64_t)5 * c->R_total, (int64_t)6 * c->R_total,
+                              do_sum ? 1 : 0, do_exchange ? 1 : 0, c->d_sacc, c->d_ctl, c->k0, c->k1,
+                              c->d_bad, c->stream));
     return XY_OK;
 }
 
@@ -264,7 +262,7 @@ void free_all(xy_ctx c)
     free_graphs(c);
     if (c->own_ang && c->ang) (void)hipFree(c->ang);
     void *ptrs[] = {c->d_lat_sweep, c->d_lat_meas, c->d_beta, c->d_pos, c->d_slot_of, c->d_ctl,
-                    c->d_partials, c->d_E, c->d_obs, c->d_macc, c->d_sacc, c->d_bad,
+                    c->d_partials, c->d_E, c->d_obs, c->d_bonds, c->d_macc, c->d_sacc, c->d_bad,
                     c->d_rq, c->d_rq_entries};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -383,13 +381,13 @@ xy_status relayout(xy_ctx c)
 {
     build_layout(c);
     const int n_items_max = std::max(c->items_sweep, c->items_meas);
-    if ((size_t)3 * n_items_max > c->partials_cap) {
+    if ((size_t)kPartials * n_items_max > c->partials_cap) {
         XY_HIP(c, hipStreamSynchronize(c->stream));
         (void)hipFree(c->d_partials);
         c->d_partials = nullptr;
-        xy_status st = dev_alloc(c, &c->d_partials, (size_t)3 * n_items_max);
+        xy_status st = dev_alloc(c, &c->d_partials, (size_t)kPartials * n_items_max);
         if (st) return st;
-        c->partials_cap = (size_t)3 * n_items_max;
+        c->partials_cap = (size_t)kPartials * n_items_max;
     }
     XY_HIP(c, hipMemcpyAsync(c->d_lat_sweep, c->lat_sweep.data(), sizeof(LatDev) * c->n_lat,
                              hipMemcpyHostToDevice, c->stream));
@@ -397,7 +395,7 @@ xy_status relayout(xy_ctx c)
                              hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
     free_graphs(c);
-    c->e_fresh = false;
+    c->e_fresh = c->bonds_fresh = false;
     return XY_OK;
 }
 
@@ -467,8 +465,9 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     if ((st = dev_alloc(c, &c->d_lat_sweep, c->n_lat)) || (st = dev_alloc(c, &c->d_lat_meas, c->n_lat)) ||
         (st = dev_alloc(c, &c->d_beta, c->R_total)) || (st = dev_alloc(c, &c->d_pos, c->R_total)) ||
         (st = dev_alloc(c, &c->d_slot_of, c->R_total)) || (st = dev_alloc(c, &c->d_ctl, 1)) ||
-        (st = dev_alloc(c, &c->d_partials, (size_t)3 * n_items_max)) ||
+        (st = dev_alloc(c, &c->d_partials, (size_t)kPartials * n_items_max)) ||
         (st = dev_alloc(c, &c->d_E, c->R_total)) || (st = dev_alloc(c, &c->d_obs, (size_t)5 * c->R_total)) ||
+        (st = dev_alloc(c, &c->d_bonds, (size_t)6 * c->R_total)) ||
         (st = dev_alloc(c, &c->d_macc, c->R_total)) || (st = dev_alloc(c, &c->d_sacc, c->R_total)) ||
         (st = dev_alloc(c, &c->d_bad, 1)))
         return bail(st);
@@ -482,7 +481,7 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
             return bail(st);
     }
 
-    c->partials_cap = (size_t)3 * n_items_max;
+    c->partials_cap = (size_t)kPartials * n_items_max;
     std::vector<int32_t> ident(c->R_total);
     {
         int p = 0;
@@ -503,7 +502,7 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     if (e == hipSuccess) e = hipMemcpy(c->d_sacc, zeros.data(), sizeof(unsigned long long) * c->R_total, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        RecheckQueue q{0u, 0u, c->rq_capacity, 0u, c->d_rq_entries};
+        RecheckQueue q{0u, 0u, c->rq_capacity, 0u, c->d_rq_entries};  // count, overflow, capacity, done
         e = hipMemcpy(c->d_rq, &q, sizeof(q), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
@@ -530,7 +529,7 @@ xy_status xy_sweep(xy_ctx c, int32_t n_metro, int32_t n_or)
     xy_status st = enqueue_sweep(c, n_metro, n_or, false);
     if (st) return st;
     c->t += 1;
-    c->e_fresh = false;
+    c->e_fresh = c->bonds_fresh = false;
     return XY_OK;
 }
 
@@ -585,7 +584,7 @@ xy_status xy_sweep_profiled(xy_ctx c, int32_t n_metro, int32_t n_or, double *ms,
         ms[2] = t;
         launches[2] = 1;
         c->t += 1;
-        c->e_fresh = false;
+        c->e_fresh = c->bonds_fresh = false;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return st;
@@ -598,8 +597,9 @@ xy_status xy_measure(xy_ctx c, double *obs, int32_t obs_on_device)
     xy_status st = enqueue_measure_kernel(c);
     if (st) return st;
     double *dst = obs_on_device ? obs : c->d_obs;
-    if ((st = enqueue_finalize(c, false, dst, 0, true, false))) return st;
+    if ((st = enqueue_finalize(c, false, dst, 0, true, false, c->d_bonds))) return st;
     c->e_fresh = true;
+    c->bonds_fresh = true;
     if (!obs_on_device) {
         XY_HIP(c, hipMemcpyAsync(obs, c->d_obs, sizeof(double) * 5 * c->R_total, hipMemcpyDeviceToHost,
                                  c->stream));
@@ -615,8 +615,9 @@ xy_status xy_exchange(xy_ctx c, int64_t *n_acc)
     xy_status st;
     if (!c->e_fresh) {
         if ((st = enqueue_measure_kernel(c))) return st;
-        if ((st = enqueue_finalize(c, false, nullptr, 0, true, false))) return st;
+        if ((st = enqueue_finalize(c, false, nullptr, 0, true, false, c->d_bonds))) return st;
         c->e_fresh = true;
+        c->bonds_fresh = true;
     }
     if ((st = enqueue_finalize(c, false, nullptr, 0, false, true))) return st;
     XY_HIP(c, launch_tick(c->d_ctl, 0u, 1u, 0u, 0, c->stream));
@@ -634,6 +635,12 @@ xy_status xy_exchange(xy_ctx c, int64_t *n_acc)
 xy_status xy_run(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int32_t exchange_every,
                  double *obs_dev)
 {
+    return xy_run_ex(c, n_sweeps, n_metro, n_or, exchange_every, obs_dev, nullptr);
+}
+
+xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int32_t exchange_every,
+                    double *obs_dev, double *bonds_dev)
+{
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
     if (n_sweeps < 0 || exchange_every < 0) return fail(c, XY_ERR_ARG, "n_sweeps and exchange_every must be >= 0");
     if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || n_metro > 255 || n_or > 65535)
@@ -644,7 +651,7 @@ xy_status xy_run(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int3
 
     // Two captured graphs: sweep + measure, and sweep + measure + exchange.
     auto get_graph = [&](int exch, hipGraphExec_t *exec) -> xy_status {
-        GraphKey key{n_metro, n_or, exch, obs_dev};
+        GraphKey key{n_metro, n_or, exch, obs_dev, bonds_dev};
         for (auto &g : c->graphs)
             if (g.key == key) {
                 *exec = g.exec;
@@ -656,9 +663,10 @@ xy_status xy_run(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int3
         c->stream = c->cap_stream;
         XY_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         xy_status st = enqueue_sweep(c, n_metro, n_or, true);
-        if (!st) st = enqueue_finalize(c, true, obs_dev, 1, true, exch != 0);
+        if (!st) st = enqueue_finalize(c, true, obs_dev, 1, true, exch != 0, bonds_dev);
         if (!st) {
-            hipError_t e = launch_tick(c->d_ctl, 0u, exch ? 1u : 0u, obs_dev ? 1u : 0u, 0, c->cap_stream);
+            hipError_t e = launch_tick(c->d_ctl, 0u, exch ? 1u : 0u, (obs_dev || bonds_dev) ? 1u : 0u, 0,
+                                       c->cap_stream);
             if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
         }
         hipGraph_t graph = nullptr;
@@ -692,7 +700,139 @@ xy_status xy_run(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, int3
         if (ex) c->tau += 1;
     }
     c->e_fresh = true;
+    c->bonds_fresh = false;
     return XY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: for each lattice, time one Metropolis and one over-relaxation
+// half-sweep of that lattice alone for every admissible (ty, tz), weight them
+// by the sweep composition, keep the fastest.  The lattice's angles and
+// acceptance counters are saved before and restored after, and the
+// near-threshold re-decision is off while timing, so tuning leaves the chain
+// untouched.
+// ---------------------------------------------------------------------------
+xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (c->prec != XY_FP32) return XY_OK;  // plain kernels have no tile choice
+    if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || reps < 1 || reps > 100)
+        return fail(c, XY_ERR_ARG, "need n_metro, n_or >= 0, n_metro + n_or >= 1, 1 <= reps <= 100");
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    LatDev *d_one = nullptr;
+    void *save = nullptr;
+    unsigned long long *save_acc = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    xy_status st = XY_OK;
+    size_t max_bytes = 0;
+    for (int l = 0; l < c->n_lat; ++l)
+        max_bytes = std::max(max_bytes, (size_t)c->R[l] * (size_t)c->lat_sweep[l].N * c->elem);
+    if ((st = dev_alloc(c, &d_one, 1)) || (st = dev_alloc(c, (char **)&save, max_bytes)) ||
+        (st = dev_alloc(c, &save_acc, c->R_total))) {
+        (void)hipFree(d_one);
+        (void)hipFree(save);
+        (void)hipFree(save_acc);
+        return st;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        st = fail(c, XY_ERR_HIP, "hipEventCreate failed");
+    if (!st && hipMemcpyAsync(save_acc, c->d_macc, sizeof(unsigned long long) * c->R_total,
+                              hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        st = fail(c, XY_ERR_HIP, "saving counters failed");
+    for (int l = 0; l < c->n_lat && !st; ++l) {
+        const LatDev &base = c->lat_sweep[l];
+        const int L = base.L, half = base.half;
+        char *lat_ang = (char *)c->ang + (size_t)base.base * c->elem;
+        const size_t bytes = (size_t)base.R * (size_t)base.N * c->elem;
+        if (hipMemcpyAsync(save, lat_ang, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+            st = fail(c, XY_ERR_HIP, "saving angles failed");
+            break;
+        }
+        Tiling best = c->tiles[l];
+        double best_cost = 1e300;
+        for (int ty : divisors(L)) {
+            if (ty * half > 8 * kBlock) continue;
+            if (ty * half < kBlock / 2 && ty != L) continue;  // mostly idle lanes
+            for (int tz : divisors(L)) {
+                if (tz < 2 && L > 2) continue;
+                if (tz > 64 && tz != L) continue;
+                Tiling t;
+                t.TY = ty;
+                t.TZ = tz;
+                t.spt = spt_for(ty * half);
+                LatDev one = base;
+                one.TY = ty;
+                one.TZ = tz;
+                one.ny = L / ty;
+                one.nz = L / tz;
+                one.items_per_slot = one.ny * one.nz;
+                one.item_base = 0;
+                const int items = one.R * one.items_per_slot;
+                if ((size_t)kPartials * items > c->partials_cap) continue;
+                if (hipMemcpyAsync(d_one, &one, sizeof(LatDev), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+                    st = fail(c, XY_ERR_HIP, "upload failed");
+                    break;
+                }
+                SweepArgs a{};
+                a.lats = d_one;
+                a.n_lat = 1;
+                a.total_items = items;
+                a.ang = c->ang;
+                a.beta = c->d_beta;
+                a.pos = c->d_pos;
+                a.ctl = c->d_ctl;
+                a.k0 = c->k0;
+                a.k1 = c->k1;
+                a.colour = 0;
+                a.substep = 0;
+                a.recheck = 0;
+                a.rq = c->d_rq;
+                a.partials = c->d_partials;
+                a.macc = c->d_macc;
+                const size_t lds = (size_t)2 * (ty + 2) * half * 2 * sizeof(float);
+                const int halo = (L > kBlock) ? 4 : 1;
+                double cost = 0.0;
+                for (int kind = 0; kind < 2 && !st; ++kind) {
+                    const int weight = kind == 0 ? n_metro : n_or;
+                    if (weight == 0) continue;
+                    const int kk = kind == 0 ? kMetro : kOver;
+                    hipError_t e = launch_tile_f32(kk, false, t.spt, halo, items, lds, a, c->stream);  // warm
+                    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r)
+                        e = launch_tile_f32(kk, false, t.spt, halo, items, lds, a, c->stream);
+                    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        st = fail(c, XY_ERR_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    cost += (double)weight * ms / reps;
+                }
+                if (st) break;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = t;
+                }
+            }
+            if (st) break;
+        }
+        if (hipMemcpyAsync(lat_ang, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess && !st)
+            st = fail(c, XY_ERR_HIP, "restoring angles failed");
+        if (!st) c->tiles[l] = best;
+    }
+    if (hipMemcpyAsync(c->d_macc, save_acc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess && !st)
+        st = fail(c, XY_ERR_HIP, "restoring counters failed");
+    (void)hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_one);
+    (void)hipFree(save);
+    (void)hipFree(save_acc);
+    if (st) return st;
+    return relayout(c);
 }
 
 xy_status xy_set_tiling(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap)
@@ -727,6 +867,23 @@ xy_status xy_get_tiling(xy_ctx c, int32_t lattice, int32_t *ty, int32_t *tz, int
     if (ty) *ty = c->tiles[lattice].TY;
     if (tz) *tz = c->tiles[lattice].TZ;
     if (grid_cap) *grid_cap = c->grid_sweep;
+    return XY_OK;
+}
+
+xy_status xy_get_bond_sums(xy_ctx c, double *out, int32_t out_on_device)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!out) return fail(c, XY_ERR_ARG, "out is NULL");
+    if (!c->bonds_fresh) {
+        xy_status st = enqueue_measure_kernel(c);
+        if (!st) st = enqueue_finalize(c, false, nullptr, 0, true, false, c->d_bonds);
+        if (st) return st;
+        c->e_fresh = true;
+        c->bonds_fresh = true;
+    }
+    XY_HIP(c, hipMemcpyAsync(out, c->d_bonds, sizeof(double) * 6 * c->R_total,
+                             out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    if (!out_on_device) XY_HIP(c, hipStreamSynchronize(c->stream));
     return XY_OK;
 }
 
@@ -798,6 +955,36 @@ xy_status xy_get_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, double *hos
     return XY_OK;
 }
 
+xy_status xy_get_sites(xy_ctx c, int32_t lattice, int32_t beta_pos, int64_t n, const int64_t *sites,
+                       double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!sites || !host))) return fail(c, XY_ERR_ARG, "bad n or NULL array");
+    if (n > ((int64_t)1 << 26)) return fail(c, XY_ERR_ARG, "at most 2^26 sites per call");
+    int slot = 0;
+    xy_status st = slot_of_position(c, lattice, beta_pos, &slot);
+    if (st || n == 0) return st;
+    const LatDev &d = c->lat_sweep[lattice];
+    for (int64_t g = 0; g < n; ++g)
+        if (sites[g] < 0 || sites[g] >= d.N) return fail(c, XY_ERR_ARG, "site index out of range");
+    int64_t *d_sites = nullptr;
+    double *d_out = nullptr;
+    if ((st = dev_alloc(c, &d_sites, (size_t)n)) || (st = dev_alloc(c, &d_out, (size_t)n))) {
+        (void)hipFree(d_sites);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(d_sites, sites, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_gather(c->prec == XY_FP32, c->ang, d.base + (int64_t)slot * d.N, d.L, n, d_sites, d_out,
+                          c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_sites);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("xy_get_sites: ") + hipGetErrorString(e));
+    return XY_OK;
+}
+
 xy_status xy_set_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, const double *host)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
@@ -831,7 +1018,7 @@ xy_status xy_set_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, const doubl
     XY_HIP(c, hipMemcpyAsync((char *)c->ang + (size_t)(d.base + (int64_t)slot * d.N) * c->elem, raw.data(),
                              raw.size(), hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
-    c->e_fresh = false;
+    c->e_fresh = c->bonds_fresh = false;
     return XY_OK;
 }
 
@@ -942,7 +1129,7 @@ xy_status xy_set_state(xy_ctx c, const void *blob, size_t size)
     XY_HIP(c, hipStreamSynchronize(c->stream));
     c->t = h.t;
     c->tau = h.tau;
-    c->e_fresh = false;
+    c->e_fresh = c->bonds_fresh = false;
     return XY_OK;
 }
 

@@ -7,6 +7,8 @@
 namespace xy {
 
 constexpr int kBlock = 256;  // threads per workgroup of the tiled and plain kernels
+// measurement partials per work item: E, Mx, My, C_x, C_y, C_z, I_x, I_y, I_z
+constexpr int kPartials = 9;
 
 // One lattice of a batch, as the kernels see it.  All offsets are in angle
 // elements (float for FP32, double for FP64).
@@ -47,7 +49,7 @@ struct RecheckQueue {
     uint32_t count;
     uint32_t overflow;     // entries that did not fit: their float32 decision stands
     uint32_t capacity;
-    uint32_t pad_;
+    uint32_t done;         // workgroups of the re-decision kernel that have finished
     RecheckEntry *entries;
 };
 
@@ -64,7 +66,7 @@ struct SweepArgs {
     int32_t substep;
     int32_t recheck;           // FP32 Metropolis: re-decide in float64 near the threshold
     RecheckQueue *rq;          // where those decisions are queued
-    double *partials;          // [items][3] (E, Mx, My) when measuring
+    double *partials;          // [items][kPartials] when measuring
     unsigned long long *macc;  // [R_total] accepted Metropolis moves by position
 };
 
@@ -79,9 +81,12 @@ hipError_t launch_init(bool fp32, bool ordered, const LatDev *lats, int n_lat,
                        hipStream_t s);
 hipError_t launch_finalize(const LatDev *lats, int n_lat, int max_R, const double *partials,
                            const double *beta, int32_t *pos, int32_t *slot_of, double *E_slot,
-                           double *obs, int use_ring, int64_t ring_stride, int do_sum,
-                           int do_exchange, unsigned long long *sacc, Ctl *ctl, uint32_t k0,
-                           uint32_t k1, int *bad, hipStream_t s);
+                           double *obs, double *bonds, int use_ring, int64_t ring_stride,
+                           int64_t bond_stride, int do_sum, int do_exchange,
+                           unsigned long long *sacc, Ctl *ctl, uint32_t k0, uint32_t k1, int *bad,
+                           hipStream_t s);
+hipError_t launch_gather(bool fp32, const void *ang, int64_t slot_base, int L, int64_t n,
+                         const int64_t *sites, double *out, hipStream_t s);
 hipError_t launch_tick(Ctl *ctl, uint32_t dt, uint32_t dtau, uint32_t dring, int set_ring,
                        hipStream_t s);
 

@@ -33,34 +33,52 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Sum (E, Mx, My) over the workgroup in a fixed order and store the item's
-// partials.  Ends with a barrier so the scratch can be reused.
-__device__ __forceinline__ void block_store_partials(double e, double mx, double my,
-                                                     double *dst)
+// Sum the kPartials measurement accumulators over the workgroup in a fixed
+// order and store the item's partials.  Ends with a barrier so the scratch
+// can be reused.
+__device__ __forceinline__ void block_store_partials(const double (&v)[kPartials], double *dst)
 {
-    __shared__ double red[kBlock / 64][3];
+    __shared__ double red[kBlock / 64][kPartials];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    e = wave_sum(e);
-    mx = wave_sum(mx);
-    my = wave_sum(my);
-    if (lane == 0) {
-        red[wv][0] = e;
-        red[wv][1] = mx;
-        red[wv][2] = my;
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) {
+        const double t = wave_sum(v[q]);
+        if (lane == 0) red[wv][q] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double se = 0.0, sx = 0.0, sy = 0.0;
-        for (int i = 0; i < kBlock / 64; ++i) {
-            se += red[i][0];
-            sx += red[i][1];
-            sy += red[i][2];
-        }
-        dst[0] = se;
-        dst[1] = sx;
-        dst[2] = sy;
+    if (threadIdx.x < kPartials) {
+        double acc = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i) acc += red[i][threadIdx.x];
+        dst[threadIdx.x] = acc;
     }
     __syncthreads();
+}
+
+// Measurement terms of one colour-1 site i with unit vector (c, s), its six
+// colour-0 neighbours split by direction (+x, -x, +y, -y, +z, -z) and the
+// colour-0 partner site at the same storage index (cz, sz):
+//   E  -= S_i . h_i                        (every bond has one colour-1 end)
+//   M  += S_i + S_partner                  (each site counted once)
+//   C_mu += S_i . (S_{i+mu} + S_{i-mu})     bonds (i, i+mu) and (i-mu, i)
+//   I_mu += sin(th_i - th_{i+mu}) - sin(th_i - th_{i-mu})
+template <typename T>
+__device__ __forceinline__ void measure_site(double (&acc)[kPartials], T c, T s, T pc, T ps,
+                                             const T (&nc)[6], const T (&ns)[6])
+{
+    const double cd = (double)c, sd = (double)s;
+    double Esum = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        const double cp = (double)nc[2 * mu], sp = (double)ns[2 * mu];
+        const double cm = (double)nc[2 * mu + 1], sm = (double)ns[2 * mu + 1];
+        const double Cm = cd * (cp + cm) + sd * (sp + sm);
+        acc[3 + mu] += Cm;
+        acc[6 + mu] += sd * (cp - cm) - cd * (sp - sm);
+        Esum += Cm;
+    }
+    acc[0] -= Esum;
+    acc[1] += cd + (double)pc;
+    acc[2] += sd + (double)ps;
 }
 
 __device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned long long *dst)
@@ -120,6 +138,20 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (block b runs on XCD b mod 8).
+// Map block ids so that each XCD walks a contiguous range of items: tiles
+// that share halo rows (neighbouring y-tiles of one slot and z-chunk) then run
+// at the same time on the same XCD and meet in its L2.  A bijection on
+// [0, G); with a persistent grid that is a multiple of 8, every id a block
+// visits stays on that block's XCD.
+__device__ __forceinline__ int xcd_item(int b, int G)
+{
+    constexpr int kXcd = 8;
+    const int q = G / kXcd, r = G - q * kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ int find_lattice(const LatDev *lats, int n_lat, int item)
 {
     int li = 0;
@@ -134,7 +166,7 @@ __device__ __forceinline__ int find_lattice(const LatDev *lats, int n_lat, int i
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t colour_rsrc(const float *base, int64_t n)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * 4), 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(uint32_t)(n * 4), 0x00020000);
 }
 
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
@@ -171,7 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
     const int tid = threadIdx.x;
     const uint32_t t_sweep = a.ctl->t;
 
-    for (int w = blockIdx.x; w < a.total_items; w += gridDim.x) {
+    for (int v = blockIdx.x; v < a.total_items; v += gridDim.x) {
+        const int w = xcd_item(v, a.total_items);
         const int li = uni(find_lattice(a.lats, a.n_lat, w));
         const LatDev d = load_lat_uniform(a.lats + li);
         const int L = d.L, half = d.half, TY = d.TY;
@@ -186,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         const float *angs = (const float *)a.ang + d.base + (int64_t)slot * d.N;
         const __amdgpu_buffer_rsrc_t rown = colour_rsrc(angs + (int64_t)a.colour * (d.N / 2), d.N / 2);
         const __amdgpu_buffer_rsrc_t roth = colour_rsrc(angs + (int64_t)(a.colour ^ 1) * (d.N / 2), d.N / 2);
+        const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(angs, 0);
         const int nsite = TY * half;
         f2 *buf0 = lds;
         f2 *buf1 = lds + (TY + 2) * half;
@@ -257,7 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         }
         lds_barrier();
 
-        double accE = 0.0, accX = 0.0, accY = 0.0;
+        double acc[kPartials];
+#pragma unroll
+        for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
         unsigned long long nacc = 0;
 
         // One plane.  pre_* were loaded one step ago and are consumed at the
@@ -271,15 +307,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
             const int z = z0 + zz;
             const uint32_t sz = (uint32_t)z * plane_b;
             {
+                // planes past the chunk (needed: other colour up to z0+TZ,
+                // ours and the halo up to z0+TZ-1) are read through an empty
+                // descriptor: the load returns 0 and moves no data
+                const bool need = zz + 3 <= d.TZ;
+                const __amdgpu_buffer_rsrc_t ro = need ? roth : rnull;
+                const __amdgpu_buffer_rsrc_t rc = need ? rown : rnull;
                 const uint32_t s3 = (uint32_t)wrapz(wrapz(z + 1) + 2) * plane_b;
                 const uint32_t s2 = (uint32_t)wrapz(wrapz(z + 1) + 1) * plane_b;
 #pragma unroll
                 for (int s = 0; s < SPT; ++s) {
-                    nxt_o[s] = bload(roth, voff[s], s3);
-                    nxt_c[s] = bload(rown, voff[s], s2);
+                    nxt_o[s] = bload(ro, voff[s], s3);
+                    nxt_c[s] = bload(rc, voff[s], s2);
                 }
 #pragma unroll
-                for (int h = 0; h < HALO; ++h) nxt_h[h] = bload(roth, hvoff[h], s2);
+                for (int h = 0; h < HALO; ++h) nxt_h[h] = bload(ro, hvoff[h], s2);
             }
 
 #pragma unroll
@@ -326,9 +368,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 if constexpr (MEAS || KIND == kMeas) {
                     if (ok[s]) {
                         const f2 sc = sincos_turns(nv);
-                        accE -= (double)sc.c * (double)hx + (double)sc.s * (double)hy;
-                        accX += (double)sc.c + (double)oc0[s].c;
-                        accY += (double)sc.s + (double)oc0[s].s;
+                        // x neighbours: same j is +x when x is even (p = 0), -x otherwise
+                        const bool podd = ((ypar[s] + z) & 1) != 0;
+                        const f2 xp = podd ? n4 : n3, xm = podd ? n3 : n4;
+                        const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, ocm[s].c};
+                        const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, ocm[s].s};
+                        measure_site(acc, sc.c, sc.s, oc0[s].c, oc0[s].s, nc, ns);
                     }
                 }
                 if constexpr (KIND != kMeas) {
@@ -359,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         }
 
         if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
-        if constexpr (MEAS || KIND == kMeas) block_store_partials(accE, accX, accY, a.partials + 3 * (int64_t)w);
+        if constexpr (MEAS || KIND == kMeas) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
     }
 }
 
@@ -367,7 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 // Re-take the queued near-threshold Metropolis decisions in float64: the six
 // neighbour angles (other colour, untouched by this half-sweep) are read
 // again, dE and exp(-beta dE) evaluated in double, and the site is corrected
-// where the float64 decision differs.  One workgroup; empties the queue.
+// where the float64 decision differs.  The last workgroup to finish empties
+// the queue for the next half-sweep.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_recheck(const LatDev *lats, float *ang,
                                                     const double *beta, const int32_t *pos,
@@ -376,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_recheck(const LatDev *lats, float *a
 {
     const double twopi = 6.283185307179586476925286766559;
     const uint32_t n = min(rq->count, rq->capacity);
-    for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const RecheckEntry en = rq->entries[e];
         const LatDev d = lats[en.li];
         const int L = d.L, half = d.half;
@@ -415,7 +461,14 @@ __global__ __launch_bounds__(kBlock) void k_recheck(const LatDev *lats, float *a
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) rq->count = 0;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&rq->done, 1u) == gridDim.x - 1) {
+            rq->count = 0;
+            rq->done = 0;
+            __threadfence();
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -443,7 +496,9 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
 
     const int64_t q = (int64_t)b * kBlock + threadIdx.x;
     const bool ok = q < d.N / 2;
-    double accE = 0.0, accX = 0.0, accY = 0.0;
+    double acc[kPartials];
+#pragma unroll
+    for (int m = 0; m < kPartials; ++m) acc[m] = 0.0;
     unsigned long long nacc = 0;
     if (ok) {
         const int j = (int)(q % half);
@@ -495,14 +550,16 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
             double s1, c1, s0, c0;
             sincos(nv, &s1, &c1);
             sincos(oth[q], &s0, &c0);
-            accE = -(c1 * hx + s1 * hy);
-            accX = c1 + c0;
-            accY = s1 + s0;
+            // neighbour order (+x, -x, +y, -y, +z, -z); nb[0] (same j) is +x when p = 0
+            const int64_t dir[6] = {p ? nb[1] : nb[0], p ? nb[0] : nb[1], nb[3], nb[2], nb[5], nb[4]};
+            double nc[6], ns[6];
+            for (int m = 0; m < 6; ++m) sincos(oth[dir[m]], &ns[m], &nc[m]);
+            measure_site(acc, c1, s1, c0, s0, nc, ns);
         }
         if constexpr (KIND != kMeas) own[q] = nv;
     }
     if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
-    if constexpr (MEAS || KIND == kMeas) block_store_partials(accE, accX, accY, a.partials + 3 * (int64_t)w);
+    if constexpr (MEAS || KIND == kMeas) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,34 +607,35 @@ __global__ void k_init(int fp32, int ordered, const LatDev *lats, int n_lat, int
 // ---------------------------------------------------------------------------
 __global__ void k_finalize(const LatDev *lats, const double *partials, const double *beta,
                            int32_t *pos, int32_t *slot_of, double *E_slot, double *obs,
-                           int use_ring, int64_t ring_stride, int do_sum, int do_exchange,
-                           unsigned long long *sacc, Ctl *ctl, uint32_t k0, uint32_t k1,
-                           int *bad)
+                           double *bonds, int use_ring, int64_t ring_stride, int64_t bond_stride,
+                           int do_sum, int do_exchange, unsigned long long *sacc, Ctl *ctl,
+                           uint32_t k0, uint32_t k1, int *bad)
 {
     const LatDev d = lats[blockIdx.x];
     const int pb = d.pos_base;
     if (do_sum) {
         // one wavefront per slot: lanes stride over the slot's items, then a
         // fixed butterfly; the order depends only on the item layout
-        double *out = obs;
+        double *out = obs, *bout = bonds;
         if (out && use_ring) out += (int64_t)ctl->ring * ring_stride;
+        if (bout && use_ring) bout += (int64_t)ctl->ring * bond_stride;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
         for (int r = wv; r < d.R; r += nw) {
-            const double *pp = partials + 3 * ((int64_t)d.item_base + (int64_t)r * d.items_per_slot);
-            double E = 0.0, mx = 0.0, my = 0.0;
-            for (int it = lane; it < d.items_per_slot; it += 64) {
-                E += pp[3 * it + 0];
-                mx += pp[3 * it + 1];
-                my += pp[3 * it + 2];
-            }
-            E = wave_sum(E);
-            mx = wave_sum(mx);
-            my = wave_sum(my);
+            const double *pp = partials + kPartials * ((int64_t)d.item_base + (int64_t)r * d.items_per_slot);
+            double v[kPartials];
+#pragma unroll
+            for (int q = 0; q < kPartials; ++q) v[q] = 0.0;
+            for (int it = lane; it < d.items_per_slot; it += 64)
+#pragma unroll
+                for (int q = 0; q < kPartials; ++q) v[q] += pp[kPartials * it + q];
+#pragma unroll
+            for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
             if (lane == 0) {
+                const double E = v[0], mx = v[1], my = v[2];
                 E_slot[pb + r] = E;
                 if (!isfinite(E) || !isfinite(mx) || !isfinite(my)) atomicOr(bad, 1);
+                const int kk = pos[pb + r];
                 if (out) {
-                    const int kk = pos[pb + r];
                     const double n = (double)d.N;
                     const double m = sqrt(mx * mx + my * my) / n;
                     double *o = out + 5 * (int64_t)(pb + kk);
@@ -586,6 +644,11 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
                     o[2] = m;
                     o[3] = m * m;
                     o[4] = (m * m) * (m * m);
+                }
+                if (bout) {
+                    double *o = bout + 6 * (int64_t)(pb + kk);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) o[q] = v[3 + q];
                 }
             }
         }
@@ -607,6 +670,21 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
             }
         }
     }
+}
+
+// Gather angles of chosen sites (natural index) of one slot, as radians.
+__global__ void k_gather(int fp32, const void *ang, int64_t slot_base, int L, int64_t n,
+                         const int64_t *sites, double *out)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int64_t i = sites[g];
+    const int64_t N = (int64_t)L * L * L;
+    const int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+    const int c = (x + y + z) & 1;
+    const int64_t src = slot_base + (int64_t)c * (N / 2) + ((int64_t)z * L + y) * (L / 2) + (x >> 1);
+    out[g] = fp32 ? (double)((const float *)ang)[src] * 6.283185307179586476925286766559
+                  : ((const double *)ang)[src];
 }
 
 __global__ void k_tick(Ctl *ctl, uint32_t dt, uint32_t dtau, uint32_t dring, int set_ring)
@@ -664,7 +742,7 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int g
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
                           int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_recheck, dim3(1), dim3(kBlock), 0, s, lats, (float *)ang, beta, pos, colour,
+    hipLaunchKernelGGL(k_recheck, dim3(16), dim3(kBlock), 0, s, lats, (float *)ang, beta, pos, colour,
                        rq, macc);
     return hipGetLastError();
 }
@@ -696,15 +774,25 @@ hipError_t launch_init(bool fp32, bool ordered, const LatDev *lats, int n_lat, i
 
 hipError_t launch_finalize(const LatDev *lats, int n_lat, int max_R, const double *partials,
                            const double *beta, int32_t *pos, int32_t *slot_of, double *E_slot,
-                           double *obs, int use_ring, int64_t ring_stride, int do_sum,
-                           int do_exchange, unsigned long long *sacc, Ctl *ctl, uint32_t k0,
-                           uint32_t k1, int *bad, hipStream_t s)
+                           double *obs, double *bonds, int use_ring, int64_t ring_stride,
+                           int64_t bond_stride, int do_sum, int do_exchange,
+                           unsigned long long *sacc, Ctl *ctl, uint32_t k0, uint32_t k1, int *bad,
+                           hipStream_t s)
 {
     int threads = 64;
     while (threads < 64 * max_R && threads < 1024) threads *= 2;
     hipLaunchKernelGGL(k_finalize, dim3(n_lat), dim3(threads), 0, s, lats, partials, beta, pos,
-                       slot_of, E_slot, obs, use_ring, ring_stride, do_sum, do_exchange, sacc, ctl,
-                       k0, k1, bad);
+                       slot_of, E_slot, obs, bonds, use_ring, ring_stride, bond_stride, do_sum,
+                       do_exchange, sacc, ctl, k0, k1, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(bool fp32, const void *ang, int64_t slot_base, int L, int64_t n,
+                         const int64_t *sites, double *out, hipStream_t s)
+{
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(kBlock), 0, s, (int)fp32, ang, slot_base, L, n,
+                       sites, out);
     return hipGetLastError();
 }
 

@@ -90,14 +90,25 @@ class Sim:
         C.check(C.lib().xy_exchange(self._ctx, None), self._ctx)
         return None
 
-    def run(self, n_sweeps, n_metro=1, n_or=1, exchange_every=1, obs=None):
-        """Graph-replayed loop; ``obs`` (optional) is a float64 CUDA tensor of
-        shape (n_sweeps, R_total, 5) receiving every sweep's observables."""
+    def run(self, n_sweeps, n_metro=1, n_or=1, exchange_every=1, obs=None, bonds=None):
+        """Graph-replayed loop.  ``obs`` (optional) is a float64 CUDA tensor of
+        shape (n_sweeps, R_total, 5) receiving every sweep's observables;
+        ``bonds`` (optional) one of shape (n_sweeps, R_total, 6) receiving the
+        bond sums (C_x, C_y, C_z, I_x, I_y, I_z) of Eq. (6)."""
         ptr = ctypes.c_void_p(obs.data_ptr()) if obs is not None else None
+        bptr = ctypes.c_void_p(bonds.data_ptr()) if bonds is not None else None
         if obs is not None:
             assert obs.dtype.itemsize == 8 and obs.numel() >= n_sweeps * self.R_total * 5
-        C.check(C.lib().xy_run(self._ctx, int(n_sweeps), int(n_metro), int(n_or),
-                               int(exchange_every), ptr), self._ctx)
+        if bonds is not None:
+            assert bonds.dtype.itemsize == 8 and bonds.numel() >= n_sweeps * self.R_total * 6
+        C.check(C.lib().xy_run_ex(self._ctx, int(n_sweeps), int(n_metro), int(n_or),
+                                  int(exchange_every), ptr, bptr), self._ctx)
+
+    def bond_sums(self):
+        """(R_total, 6) bond sums C_x, C_y, C_z, I_x, I_y, I_z of the current state."""
+        out = np.zeros((self.R_total, 6), dtype=np.float64)
+        C.check(C.lib().xy_get_bond_sums(self._ctx, out.ctypes.data_as(ctypes.c_void_p), 0), self._ctx)
+        return out
 
     def sweep_profiled(self, n_metro=1, n_or=1):
         """xy_sweep with per-kernel HIP-event timing: returns
@@ -107,6 +118,12 @@ class Sim:
         C.check(C.lib().xy_sweep_profiled(self._ctx, int(n_metro), int(n_or), ms, n), self._ctx)
         keys = ("metro", "over", "other")
         return dict(zip(keys, list(ms))), dict(zip(keys, list(n)))
+
+    def autotune(self, n_metro=1, n_or=1, reps=3):
+        """Time the admissible tilings of every lattice and keep the fastest
+        (the chain state is saved and restored around the timing)."""
+        C.check(C.lib().xy_autotune(self._ctx, int(n_metro), int(n_or), int(reps)), self._ctx)
+        return [self.get_tiling(l) for l in range(len(self.L))]
 
     def set_tiling(self, lattice, ty, tz, grid_cap=0):
         C.check(C.lib().xy_set_tiling(self._ctx, int(lattice), int(ty), int(tz), int(grid_cap)), self._ctx)
@@ -123,6 +140,15 @@ class Sim:
         out = np.empty(n, dtype=np.float64)
         C.check(C.lib().xy_get_angles(self._ctx, lattice, beta_pos,
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
+        return out
+
+    def get_sites(self, sites, lattice=0, beta_pos=0):
+        """Angles (radians) of the given natural site indices."""
+        idx = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.empty(idx.size, dtype=np.float64)
+        C.check(C.lib().xy_get_sites(self._ctx, lattice, beta_pos, idx.size,
+                                     idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
         return out
 
     def set_angles(self, theta, lattice=0, beta_pos=0):

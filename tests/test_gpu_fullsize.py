@@ -1,0 +1,117 @@
+"""Parity at the benchmark's full size (L = 160 x 32 replicas, in the launch
+shape bench.py times) and at the largest lattice the library accepts
+(L = 1024), through the C ABI.
+
+Full size: whole replicas are read back and every site of a half-sweep is
+compared with the oracle's half-sweep from the same state.  L = 1024 (4.3 GB
+of float32 angles): sampled sites against the closed forms of the random
+start and of a beta = 0 Metropolis sweep (bit-exact), and energy
+conservation of over-relaxation (a property that holds at any size).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.philox_py as P
+from gpu_util import circ, colour_mask, field_numpy
+
+pytestmark = pytest.mark.gpu
+
+L_BENCH, R_BENCH = 160, 32
+
+
+def make(L, betas, seed, prec="fp32", start="random"):
+    from paper_1211_0780_amd.sim import Sim
+    return Sim(L, betas, seed=seed, prec=prec, start=start)
+
+
+@pytest.fixture(scope="module")
+def bench_sim(gpu):
+    betas = np.linspace(0.4538, 0.4546, R_BENCH)
+    s = make(L_BENCH, [betas], 4)
+    s.set_tiling(0, 8, 20, 0)   # the launch shape bench.py times
+    yield s, betas
+    s.close()
+
+
+def test_full_size_over_relaxation_every_site(bench_sim):
+    s, betas = bench_sim
+    L = L_BENCH
+    starts = {k: s.get_angles(0, k) for k in (0, R_BENCH - 1)}
+    s.sweep(0, 1)
+    m0 = colour_mask(L, 0)
+    for k, before in starts.items():
+        after = s.get_angles(0, k)
+        ref = before.copy()
+        oracle.or_half(ref, L, 0)
+        hx, hy = field_numpy(before, L)
+        bound = np.maximum(2e-5, 16 * 2.0 ** -24 * 6 / np.maximum(np.hypot(hx, hy), 1e-30))
+        assert np.all((circ(after, ref) <= bound)[m0])
+        mid = before.copy()
+        mid[m0] = after[m0]
+        ref = mid.copy()
+        oracle.or_half(ref, L, 1)
+        hx, hy = field_numpy(mid, L)
+        bound = np.maximum(2e-5, 16 * 2.0 ** -24 * 6 / np.maximum(np.hypot(hx, hy), 1e-30))
+        assert np.all((circ(after, ref) <= bound)[~m0])
+
+
+def test_full_size_metropolis_every_site(bench_sim):
+    s, betas = bench_sim
+    L, seed = L_BENCH, 4
+    k = 5
+    t = s.counters()[0]
+    before = s.get_angles(0, k)
+    s.sweep(1, 0)
+    after = s.get_angles(0, k)
+    key = P.key_of(seed)
+    m0 = colour_mask(L, 0)
+    ref = before.copy()
+    oracle.metro_half(ref, L, betas[k], seed, t, 0, k, 0, 0)
+    d = circ(after, ref)[m0]
+    # proposals are exact in turns: agreeing sites match to float rounding of 2 pi u
+    bad = np.flatnonzero(d > 1e-6)
+    hx, hy = field_numpy(before, L)
+    idx = np.flatnonzero(m0)[bad]
+    for i in idx:
+        r = P.philox4x32_10(P.counter(int(i), t, 0, k, P.PHASE_METRO, 0), key)
+        prop, u = 2 * np.pi * P.uniform(r[0]), P.uniform(r[1])
+        dE = (np.cos(before[i]) - np.cos(prop)) * hx[i] + (np.sin(before[i]) - np.sin(prop)) * hy[i]
+        assert abs(u - np.exp(-betas[k] * dE)) < 1e-6
+    assert bad.size <= 5
+
+
+def test_full_size_measurement(bench_sim):
+    s, betas = bench_sim
+    obs = s.measure()
+    N = L_BENCH ** 3
+    for k in (0, 17):
+        ref = oracle.measure(s.get_angles(0, k), L_BENCH)
+        assert abs(obs[k, 0] - ref[0]) <= 1e-6 * N
+        assert abs(obs[k, 2] - ref[2]) <= 1e-6
+
+
+def test_max_lattice_sampled(gpu):
+    import torch
+    L, seed = 1024, 77
+    N = L ** 3
+    if torch.cuda.get_device_properties(0).total_memory < 16 * N:
+        pytest.skip("device too small for L = 1024")
+    s = make(L, [[0.0]], seed)
+    rng = np.random.default_rng(1)
+    sites = np.unique(np.concatenate([rng.integers(0, N, 4000), [0, N - 1, L - 1, N - L]]))
+    key = P.key_of(seed)
+    got = s.get_sites(sites)
+    want = np.array([2 * np.pi * P.uniform(P.philox4x32_10(P.counter(int(i), 0, 0, 0, P.PHASE_INIT, 0), key)[0])
+                     for i in sites])
+    assert np.array_equal(got, want)
+    s.sweep(1, 0)
+    got = s.get_sites(sites)
+    want = np.array([2 * np.pi * P.uniform(P.philox4x32_10(P.counter(int(i), 0, 0, 0, P.PHASE_METRO, 0), key)[0])
+                     for i in sites])
+    assert np.array_equal(got, want)
+    E0 = s.measure()[0, 0]
+    s.sweep(0, 2)
+    E1 = s.measure()[0, 0]
+    assert abs(E1 - E0) <= 1e-7 * N
+    s.close()

@@ -14,6 +14,7 @@ Tolerances:
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import oracle.philox_py as P
@@ -248,3 +249,50 @@ def test_exchange_counts_and_bijection(gpu):
     perm = s.permutation()
     assert sorted(perm) == list(range(8))
     assert acc[-1] == 0 and acc.sum() > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bond_sums_match_oracle(gpu, prec):
+    """The sums behind Eq. (6), C_mu and I_mu per direction, on identical states."""
+    L = 12
+    N = L ** 3
+    s = make(L, [0.3, 0.5, 0.7], 13, prec)
+    for _ in range(3):
+        s.sweep(1, 2)
+    got = s.bond_sums()
+    tol = 1e-9 if prec == "fp64" else 2e-6
+    for k in range(3):
+        ref = oracle.bond_sums(s.get_angles(0, k), L)
+        assert np.allclose(got[k], ref, rtol=0, atol=tol * N), (got[k], ref)
+    obs = s.measure()
+    assert np.allclose(obs[:, 0], -got[:, :3].sum(axis=1), rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bond_sums_spin_wave(gpu, prec):
+    L = 8
+    N = L ** 3
+    s = make(L, [0.1], 3, prec)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    q = np.array([1, 2, 3])
+    s.set_angles((2 * np.pi * (q[0] * x + q[1] * y + q[2] * z) / L).ravel())
+    b = s.bond_sums()[0]
+    a = 2 * np.pi * q / L
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    assert np.allclose(b[:3], N * np.cos(a), atol=tol * N)
+    assert np.allclose(b[3:], -N * np.sin(a), atol=tol * N)
+
+
+def test_bond_sums_ring_matches_eager(gpu):
+    betas = [0.44, 0.45, 0.46]
+    a = make(10, betas, 9, "fp32")
+    b = make(10, betas, 9, "fp32")
+    n = 4
+    bonds = torch.zeros((n, 3, 6), dtype=torch.float64, device=gpu)
+    a.run(n, 1, 2, exchange_every=1, bonds=bonds)
+    torch.cuda.synchronize()
+    for sidx in range(n):
+        b.sweep(1, 2)
+        eb = b.bond_sums()
+        assert np.allclose(bonds[sidx].cpu().numpy(), eb, rtol=1e-12, atol=1e-8)
+        b.exchange()

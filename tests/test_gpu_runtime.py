@@ -131,3 +131,21 @@ def test_beta_zero_moments_on_gpu(gpu):
     assert abs(e.mean()) < 4 * np.sqrt(3 / (2 * N) / n)
     assert abs(N * m2.mean() - 1) < 4 / np.sqrt(n)
     assert abs(N * N * m4.mean() - (2 - 1 / N)) < 4 * np.sqrt(20 / n)
+
+
+def test_autotune_leaves_the_chain_untouched(gpu):
+    betas = list(np.linspace(0.44, 0.46, 3))
+    a = make(24, betas, 17)
+    b = make(24, betas, 17)
+    a.run(2, 1, 2, exchange_every=1)
+    b.run(2, 1, 2, exchange_every=1)
+    before = gpu_states(a), a.metro_accepts(), a.counters(), a.permutation()
+    tiles = a.autotune(1, 4, reps=1)
+    ty, tz, _ = tiles[0]
+    assert 24 % ty == 0 and 24 % tz == 0
+    assert np.array_equal(gpu_states(a), before[0])
+    assert np.array_equal(a.metro_accepts(), before[1])
+    assert a.counters() == before[2] and a.permutation() == before[3]
+    a.run(3, 1, 2, exchange_every=1)
+    b.run(3, 1, 2, exchange_every=1)
+    assert np.array_equal(gpu_states(a), gpu_states(b))

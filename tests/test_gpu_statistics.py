@@ -1,0 +1,117 @@
+"""Long-run statistical parity (same equilibrium law) on the GPU.
+
+GPU chains against the oracle's chain (configs[0]-like single lattice, and a
+small parallel-tempering ladder), float32 against float64 kernels on the
+same ladders, exchange on against off, and the Binder crossing of the
+batched finite-size-scaling set.  Averages use binning (20 bins after
+discarding 20 % as equilibration); two runs agree when
+|a - b| <= Z * sqrt(sa^2 + sb^2), with Z = 4 for the families of many
+observables (a Bonferroni-style bound) and Z = 3 otherwise.  The z-scores are
+printed for the record.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from stats_util import binned_mean, binned_ratio
+
+pytestmark = pytest.mark.gpu
+
+
+def make(L, betas, seed, prec="fp32", start="random"):
+    from paper_1211_0780_amd.sim import Sim
+    return Sim(L, betas, seed=seed, prec=prec, start=start)
+
+
+def gpu_series(sim, n, n_metro, n_or, exchange_every):
+    obs = torch.zeros((n, sim.R_total, 5), dtype=torch.float64, device="cuda")
+    sim.run(n, n_metro, n_or, exchange_every=exchange_every, obs=obs)
+    torch.cuda.synchronize()
+    return obs.cpu().numpy()
+
+
+def summary(o):
+    """Per position: (mean, err) of e, |m|, m^2, m^4 and U_L."""
+    out = []
+    for p in range(o.shape[1]):
+        row = [binned_mean(o[:, p, c]) for c in (1, 2, 3, 4)]
+        row.append(binned_ratio(o[:, p, 4], o[:, p, 3], f=lambda a, b: 1 - a / (3 * b * b)))
+        out.append(row)
+    return out
+
+
+def compare(a, b, Z, label):
+    worst = 0.0
+    names = ("e", "|m|", "m2", "m4", "U_L")
+    for p, (ra, rb) in enumerate(zip(a, b)):
+        for name, (ma, ea), (mb, eb) in zip(names, ra, rb):
+            z = (ma - mb) / np.hypot(ea, eb)
+            worst = max(worst, abs(z))
+            assert abs(z) <= Z, f"{label} pos {p} {name}: {ma} vs {mb} (z = {z:.2f})"
+    print(f"[{label}] max |z| = {worst:.2f}")
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_lattice_long_run_matches_oracle(gpu, prec):
+    """L = 8, beta = 0.4542, 1 Metropolis + 1 over-relaxation, 10^4 sweeps."""
+    L, beta, seed, n = 8, 0.4542, 1, 10000
+    s = make(L, [[beta]], seed, prec)
+    og = gpu_series(s, n, 1, 1, 0)
+    _, oo, _, _ = oracle.run(L, [beta], seed, n, 1, 1, exchange_every=0)
+    compare(summary(og), summary(oo), 3, f"L=8 {prec} vs oracle")
+
+
+def test_tempering_ladder_long_run_matches_oracle(gpu):
+    """L = 8, four replicas over [0.40, 0.50], exchange every sweep, FP32."""
+    L, seed, n = 8, 2, 10000
+    betas = list(np.linspace(0.40, 0.50, 4))
+    s = make(L, [betas], seed)
+    og = gpu_series(s, n, 1, 2, 1)
+    _, oo, _, sacc = oracle.run(L, betas, seed, n, 1, 2, exchange_every=1)
+    compare(summary(og), summary(oo), 4, "L=8 PT fp32 vs oracle")
+
+
+def test_exchange_does_not_change_equilibrium(gpu):
+    L, n = 12, 8000
+    betas = list(np.linspace(0.42, 0.48, 6))
+    a = gpu_series(make(L, [betas], 11), n, 1, 3, 1)
+    b = gpu_series(make(L, [betas], 12), n, 1, 3, 0)
+    compare(summary(a), summary(b), 4, "PT on vs off")
+
+
+def test_fp32_matches_fp64_on_a_ladder(gpu):
+    """configs[2]-like: L = 64, 32 replicas over [0.4530, 0.4554], 1 + 8,
+    float32 (with float64 near-threshold re-decision) against the all-float64
+    kernels, both with exchange every sweep."""
+    L, n = 64, 2000
+    betas = list(np.linspace(0.4530, 0.4554, 32))
+    a = gpu_series(make(L, [betas], 3, "fp32"), n, 1, 8, 1)
+    b = gpu_series(make(L, [betas], 3, "fp64"), n, 1, 8, 1)
+    compare(summary(a), summary(b), 4, "L=64 fp32 vs fp64")
+
+
+def test_fss_batch_binder_crossing(gpu):
+    """configs[4]: L in {24, 32, 48, 64, 96, 128}, 16 replicas each over
+    [0.452, 0.456], one launch per half-sweep for the whole batch, graph
+    replayed, autotuned tiles.  Sec. III: U_L curves cross at
+    beta_c = 1/2.2019 = 0.45415, inside the ladder: the smallest lattice has
+    the larger U_L at the low end of the ladder and the smaller at the top."""
+    Ls = [24, 32, 48, 64, 96, 128]
+    betas = list(np.linspace(0.452, 0.456, 16))
+    s = make(Ls, [betas] * len(Ls), 5)
+    s.autotune(1, 10, reps=2)
+    n = 3000
+    o = gpu_series(s, n, 1, 10, 1)
+    U = {}
+    for li, L in enumerate(Ls):
+        for k in (0, 15):
+            p = s.pos_base[li] + k
+            U[(L, k)] = binned_ratio(o[:, p, 4], o[:, p, 3], f=lambda a, b: 1 - a / (3 * b * b), discard=0.3)
+    for k in (0, 15):
+        print("[fss] beta", betas[k], {L: round(U[(L, k)][0], 4) for L in Ls})
+    lo_s, lo_b = U[(24, 0)], U[(128, 0)]
+    hi_s, hi_b = U[(24, 15)], U[(128, 15)]
+    assert lo_s[0] - lo_b[0] > 2 * np.hypot(lo_s[1], lo_b[1])
+    assert hi_b[0] - hi_s[0] > 2 * np.hypot(hi_s[1], hi_b[1])

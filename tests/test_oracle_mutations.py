@@ -17,8 +17,8 @@ SRC_PATH = os.path.join(ROOT, "oracle", "xy_oracle.c")
 MUTATIONS = {
     "metropolis_dE_sign": ("dE += cos(th_old - thj) - cos(th_new - thj);",
                            "dE += cos(th_new - thj) - cos(th_old - thj);"),
-    "metropolis_drops_a_neighbour": ("for (int n = 0; n < 6; ++n) {\n                    double thj",
-                                     "for (int n = 0; n < 5; ++n) {\n                    double thj"),
+    "metropolis_drops_a_neighbour": ("for (int n = 0; n < 6; ++n) {\n        double thj",
+                                     "for (int n = 0; n < 5; ++n) {\n        double thj"),
     "metropolis_half_beta": ("if (u < exp(-beta * dE)) {", "if (u < exp(-0.5 * beta * dE)) {"),
     "or_factor_one": ("double f = 2.0 * (Sx * Hx + Sy * Hy) / H2;",
                       "double f = 1.0 * (Sx * Hx + Sy * Hy) / H2;"),
