@@ -241,6 +241,12 @@ xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int
 xy_status xy_autotune(xy_ctx ctx, int32_t n_metro, int32_t n_or, int32_t reps);
 xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
 
+/* Cumulative accepted exchanges per position index (R_total entries; entry
+ * p counts swaps of pair (p, p+1) of its lattice; the last entry of each
+ * lattice stays 0).  Pair k is attempted at exchange steps tau with
+ * tau = k (mod 2).  Waits. */
+xy_status xy_get_swap_accepts(xy_ctx ctx, int64_t *n_acc);
+
 /*
  * Checkpoint: the whole chain state (angles, permutation, t, tau, seed,
  * ladders, acceptance counters) as an opaque blob.  With blob == NULL, *size

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM",
 EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange", "xy_run",
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
-           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums"]
+           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts"]
 
 
 class XYConfig(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib():
         L.xy_run_ex.restype = i32
         L.xy_get_bond_sums.argtypes = [vp, vp, i32]
         L.xy_get_bond_sums.restype = i32
+        L.xy_get_swap_accepts.argtypes = [vp, i64p]
+        L.xy_get_swap_accepts.restype = i32
         L.xy_destroy.argtypes = [vp]
         L.xy_destroy.restype = None
         _lib = L

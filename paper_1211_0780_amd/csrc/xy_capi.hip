@@ -904,6 +904,18 @@ xy_status xy_get_permutation(xy_ctx c, int32_t lattice, int32_t *slot)
     return sync_stream(c);
 }
 
+xy_status xy_get_swap_accepts(xy_ctx c, int64_t *n_acc)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!n_acc) return fail(c, XY_ERR_ARG, "n_acc is NULL");
+    std::vector<unsigned long long> v(c->R_total);
+    XY_HIP(c, hipMemcpyAsync(v.data(), c->d_sacc, sizeof(unsigned long long) * c->R_total,
+                             hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->R_total; ++i) n_acc[i] = (int64_t)v[i];
+    return XY_OK;
+}
+
 xy_status xy_get_metro_accepts(xy_ctx c, int64_t *n_acc)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");

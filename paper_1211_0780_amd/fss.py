@@ -1,0 +1,90 @@
+"""Finite-size-scaling summary of a batched run (host driver over the C ABI).
+
+Runs a batch of lattice sizes, each with the same beta ladder, in one context
+(one launch per half-sweep for the whole batch, graph-replayed, autotuned
+tiles), records per sweep the observables and the stiffness bond sums, and
+reports per L and beta: e, U_L (Eq. (5)), Q_2 (Eq. (11)), rho_s L (Eqs. (6),
+(8)) with binning errors, plus the crossings of U_L and of rho_s L between
+successive sizes (Sec. III: both cross at T_c).  It is a miniature of the
+paper's analysis for small L, not a reproduction of its exponents.
+
+    python -m paper_1211_0780_amd.fss --L 8 16 --sweeps 4000
+"""
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import analysis as A
+
+
+def run_batch(Ls, betas, seed=5, n_sweeps=10000, n_metro=1, n_or=10, exchange_every=1,
+              discard=0.3, autotune=True):
+    import torch
+    from .sim import Sim
+
+    sim = Sim(Ls, [betas] * len(Ls), seed=seed, prec="fp32")
+    if autotune:
+        sim.autotune(n_metro, n_or, reps=2)
+    R_total = sim.R_total
+    obs = torch.zeros((n_sweeps, R_total, 5), dtype=torch.float64, device=sim.device)
+    bonds = torch.zeros((n_sweeps, R_total, 6), dtype=torch.float64, device=sim.device)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(sim.stream)
+    sim.run(n_sweeps, n_metro, n_or, exchange_every=exchange_every, obs=obs, bonds=bonds)
+    t1.record(sim.stream)
+    torch.cuda.synchronize()
+    secs = t0.elapsed_time(t1) / 1e3
+    o = obs.cpu().numpy()
+    b = bonds.cpu().numpy()
+    sites = sum(L ** 3 for L in Ls) * len(betas)
+    swaps = sim.swap_accepts()
+    n_ex = n_sweeps // exchange_every if exchange_every else 0
+    result = {"L": list(Ls), "betas": [float(x) for x in betas], "n_sweeps": n_sweeps,
+              "site_updates_per_s": n_sweeps * (n_metro + n_or) * sites / secs,
+              "tiling": [sim.get_tiling(l) for l in range(len(Ls))], "per_L": {}}
+    for li, L in enumerate(Ls):
+        N = L ** 3
+        rows = []
+        for k, beta in enumerate(betas):
+            p = sim.pos_base[li] + k
+            e = A.binned(o[:, p, 1], discard=discard)
+            U = A.binder(o[:, p, 3], o[:, p, 4], discard=discard)
+            Q = A.q2(o[:, p, 3], o[:, p, 4], discard=discard)
+            rho = A.stiffness(b[:, p, :], beta, N, discard=discard)
+            rows.append({"beta": float(beta), "e": e, "U": U, "Q2": Q,
+                         "rhoL": (rho[0] * L, rho[1] * L)})
+        rates = A.swap_rates(swaps[sim.pos_base[li]: sim.pos_base[li] + len(betas)], n_ex) if n_ex else []
+        result["per_L"][str(L)] = {"rows": rows, "swap_rates": [float(r) for r in rates]}
+    cross = []
+    for La, Lb in zip(Ls[:-1], Ls[1:]):
+        ra, rb = result["per_L"][str(La)]["rows"], result["per_L"][str(Lb)]["rows"]
+        for key in ("U", "rhoL"):
+            ya = np.array([r[key][0] for r in ra]); ea = np.array([r[key][1] for r in ra])
+            yb = np.array([r[key][0] for r in rb]); eb = np.array([r[key][1] for r in rb])
+            bc, err = A.crossing(betas, ya, ea, yb, eb)
+            cross.append({"pair": [La, Lb], "quantity": key, "beta_cross": bc, "err": err})
+    result["crossings"] = cross
+    sim.close()
+    return result
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--L", type=int, nargs="+", default=[24, 32, 48, 64, 96, 128])
+    ap.add_argument("--beta", type=float, nargs=2, default=[0.452, 0.456])
+    ap.add_argument("--replicas", type=int, default=16)
+    ap.add_argument("--sweeps", type=int, default=10000)
+    ap.add_argument("--n-or", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args(argv)
+    betas = np.linspace(args.beta[0], args.beta[1], args.replicas)
+    res = run_batch(args.L, betas, seed=args.seed, n_sweeps=args.sweeps, n_or=args.n_or)
+    json.dump(res, sys.stdout)
+    print()
+
+
+if __name__ == "__main__":
+    main()

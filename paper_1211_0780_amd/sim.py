@@ -172,6 +172,12 @@ class Sim:
         C.check(C.lib().xy_get_metro_accepts(self._ctx, acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self._ctx)
         return acc
 
+    def swap_accepts(self):
+        """Cumulative accepted exchanges of pair (p, p+1) per position index."""
+        acc = np.zeros(self.R_total, dtype=np.int64)
+        C.check(C.lib().xy_get_swap_accepts(self._ctx, acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self._ctx)
+        return acc
+
     def get_state(self):
         size = ctypes.c_size_t()
         C.check(C.lib().xy_get_state(self._ctx, None, ctypes.byref(size)), self._ctx)
