@@ -8,9 +8,12 @@ step.  A "step" is one such sweep of all 32 replicas (graph-replayed).
 
 Prints one JSON line:
   value     site-updates per second over the timed steps (inputs resident in HBM)
-  roofline  the over-relaxation half-sweep kernel (the dominant one) against
-            8 TB/s HBM, using 12 algorithmic bytes per site-update, timed with
-            HIP events around each launch on the simulation's stream
+  roofline  the dominant kernel, the fused over-relaxation substep (one launch
+            updates both colours), against 8 TB/s HBM at 12 algorithmic bytes
+            per site-update (the unfused half-sweep's reads and writes; the
+            fused pass moves less, so this fraction can exceed what an unfused
+            kernel could reach), timed with HIP events around each launch on
+            the simulation's stream
   cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload
   fp64_plain    the plain FP64 single-replica kernels at L = 160, for reference
 """
@@ -35,6 +38,7 @@ L, R, SEED = 160, 32, 4
 BETA_LO, BETA_HI = 0.4538, 0.4546
 N_METRO, N_OR = 1, 10
 DEFAULT_TILING = "8x20"
+DEFAULT_TILING_FUSED = "5x20"
 
 
 def _oracle_one_sweep(args):
@@ -83,10 +87,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash):
-    """HBM bytes per launch of the over-relaxation kernel from the committed
+def traffic_path(kind):
+    name = "traffic_fused_over_relax_L160x32.json" if kind == "fused" else "traffic_over_relax_L160x32.json"
+    return os.path.join(ROOT, "profiles", name)
+
+
+def load_traffic(kernel_hash, kind):
+    """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_over_relax_L160x32.json")
+    path = traffic_path(kind)
     try:
         with open(path) as fh:
             d = json.load(fh)
@@ -103,14 +112,14 @@ COPY_BYTES = 1 << 30
 def traffic_probe(sim, dev):
     """Workload for `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`: a plain
     device copy of COPY_BYTES (the calibration kernel: it must read and write
-    exactly that many bytes), then one over-relaxation substep (two half-sweep
-    launches) of the bench configuration."""
+    exactly that many bytes), then two over-relaxation substeps of the bench
+    configuration (fused: two launches; unfused: four)."""
     import torch
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    sim.sweep(0, 1)
+    sim.sweep(0, 2)
     torch.cuda.synchronize()
     print("[bench] traffic probe done", file=sys.stderr, flush=True)
 
@@ -134,7 +143,10 @@ def digest_traffic(fetch_csv, write_csv):
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _pmc_rows(path, counter)
         copy = [v for n, v in rows if "elementwise" in n or "copy" in n.lower()]
-        over = [v for n, v in rows if "k_tile_f32" in n and ("ILi1E" in n or "<1," in n or "(xy::Kind)1" in n)]
+        fused = [v for n, v in rows if "k_or2_f32" in n]
+        half = [v for n, v in rows if "k_tile_f32<1," in n]
+        over = fused or half
+        kind = "fused" if fused else "half"
         if not copy or not over:
             raise SystemExit(f"{path}: copy or over-relaxation dispatches not found")
         scale = COPY_BYTES / max(copy)
@@ -143,8 +155,9 @@ def digest_traffic(fetch_csv, write_csv):
         out[f"{key}_scale_bytes_per_unit"] = scale
         out[f"{key}_bytes_per_launch"] = out[f"{key}_counter_per_launch"] * scale
     out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
-    out["algorithmic_bytes_per_launch"] = BYTES_PER_UPDATE_F32 * R * L ** 3 / 2
-    path = os.path.join(ROOT, "profiles", "traffic_over_relax_L160x32.json")
+    out["kernel"] = kind
+    out["algorithmic_bytes_per_launch"] = BYTES_PER_UPDATE_F32 * R * L ** 3 / (1 if kind == "fused" else 2)
+    path = traffic_path(kind)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -162,6 +175,10 @@ def main():
                     help="'TYxTZ' for the tiled half-sweep, or 'auto' to run the autotuner "
                          f"(default {DEFAULT_TILING}: the autotuner's pick for this workload, fixed "
                          "so that timing and counter runs use the same launch shape)")
+    ap.add_argument("--tiling-fused", default=DEFAULT_TILING_FUSED,
+                    help="'TYxTZ' for the fused over-relaxation kernel (ignored with --tiling auto)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="run over-relaxation as two half-sweep kernels per substep")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the workload for HBM counter collection: a plain 1 GiB device "
                          "copy, then one over-relaxation substep of the bench configuration")
@@ -184,7 +201,7 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     betas = np.linspace(BETA_LO, BETA_HI, R)
-    sim = Sim(L, [betas], seed=SEED, prec="fp32")
+    sim = Sim(L, [betas], seed=SEED, prec="fp32", fused_or=not args.unfused)
     N = L ** 3
     if args.tiling == "auto":
         print("[bench] autotune", file=sys.stderr, flush=True)
@@ -192,7 +209,11 @@ def main():
     else:
         ty, tz = (int(v) for v in args.tiling.split("x"))
         sim.set_tiling(0, ty, tz, 0)
+        if not args.unfused:
+            ty2, tz2 = (int(v) for v in args.tiling_fused.split("x"))
+            sim.set_tiling_fused(0, ty2, tz2)
         tiling = sim.get_tiling(0)
+    tiling_fused = sim.get_tiling_fused(0)
     if args.traffic_probe:
         traffic_probe(sim, dev)
         return
@@ -223,19 +244,22 @@ def main():
 
     # per-kernel device time, HIP events around each launch on the same stream
     print(f"[bench] per-kernel timing over {args.profile_steps} sweeps", file=sys.stderr, flush=True)
-    tot = {"metro": 0.0, "over": 0.0, "other": 0.0}
-    cnt = {"metro": 0, "over": 0, "other": 0}
+    tot, cnt = {}, {}
     for _ in range(args.profile_steps):
         ms, n = sim.sweep_profiled(N_METRO, N_OR)
-        for k in tot:
-            tot[k] += ms[k]
-            cnt[k] += n[k]
-    over_ms = tot["over"] / max(cnt["over"], 1)
-    metro_ms = tot["metro"] / max(cnt["metro"], 1)
-    bytes_per_launch = BYTES_PER_UPDATE_F32 * R * N / 2
-    achieved = bytes_per_launch / (over_ms / 1e3) / 1e9
+        for k in ms:
+            tot[k] = tot.get(k, 0.0) + ms[k]
+            cnt[k] = cnt.get(k, 0) + n[k]
+    avg = {k: (tot[k] / cnt[k] if cnt[k] else None) for k in tot}
     khash = kernel_source_hash()
-    traffic = load_traffic(khash)
+    if cnt["over_fused"]:
+        kname, kms = "fused over-relaxation substep (k_or2_f32: both colours per launch)", avg["over_fused"]
+        bytes_per_launch = BYTES_PER_UPDATE_F32 * R * N
+    else:
+        kname, kms = "over-relaxation half-sweep (k_tile_f32<kOver>)", avg["over"]
+        bytes_per_launch = BYTES_PER_UPDATE_F32 * R * N / 2
+    achieved = bytes_per_launch / (kms / 1e3) / 1e9
+    traffic = load_traffic(khash, "fused" if cnt["over_fused"] else "half")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -243,11 +267,11 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "over-relaxation half-sweep (k_tile_f32<kOver>)",
-        "avg_launch_ms": round(over_ms, 4),
+        "kernel": kname,
+        "avg_launch_ms": round(kms, 4),
         "algorithmic_bytes_per_launch": bytes_per_launch,
-        "metro_avg_launch_ms": round(metro_ms, 4),
-        "metro_achieved_GBs": round(bytes_per_launch / (metro_ms / 1e3) / 1e9, 1),
+        "bytes_per_update_counted": BYTES_PER_UPDATE_F32,
+        "avg_launch_ms_by_kernel": {k: (round(v, 4) if v is not None else None) for k, v in avg.items()},
         "kernel_source_hash": khash,
     }
     sim.close()
@@ -294,6 +318,7 @@ def main():
             "L": L, "replicas": R, "n_metro": N_METRO, "n_or": N_OR, "seed": SEED,
             "site_updates_per_step": (N_METRO + N_OR) * N * R,
             "tiling": {"ty": tiling[0], "tz": tiling[1], "grid_cap": tiling[2]},
+            "tiling_fused": {"ty": tiling_fused[0], "tz": tiling_fused[1]},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

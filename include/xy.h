@@ -81,6 +81,9 @@ typedef enum {
 
 /* xy_config.flags */
 #define XY_F_NO_RECHECK  0x1u /* FP32: take Metropolis decisions in float32 only */
+#define XY_F_NO_FUSED_OR 0x2u /* FP32: run every over-relaxation substep as two half-sweep
+                                 kernels instead of one fused kernel (the fused kernel is
+                                 used when every L <= 256; it needs a second angle buffer) */
 
 typedef struct {
     int32_t n_lattices;          /* >= 1 */
@@ -167,10 +170,11 @@ xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
 
 /*
  * xy_sweep with every kernel launch bracketed by HIP events on the
- * context's stream (profiling aid; same result as xy_sweep).  ms[0], ms[1]
- * receive the summed device time of the Metropolis and over-relaxation
- * half-sweep kernels, ms[2] of everything else the sweep launched;
- * launches[0..2] the matching kernel counts.  Waits.
+ * context's stream (profiling aid; same result as xy_sweep).  ms[0..3]
+ * receive the summed device time of the Metropolis half-sweeps, the
+ * over-relaxation half-sweeps, the fused over-relaxation substeps (one
+ * launch updates both colours) and everything else the sweep launched;
+ * launches[0..3] the matching kernel counts.  Waits.
  */
 xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *ms,
                             int32_t *launches);
@@ -240,6 +244,11 @@ xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int
  */
 xy_status xy_autotune(xy_ctx ctx, int32_t n_metro, int32_t n_or, int32_t reps);
 xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
+
+/* The same for the fused over-relaxation kernel (its own tiles; rows and
+ * planes as above).  XY_ERR_UNSUPPORTED when the context does not fuse. */
+xy_status xy_set_tiling_fused(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz);
+xy_status xy_get_tiling_fused(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz);
 
 /* Cumulative accepted exchanges per position index (R_total entries; entry
  * p counts swaps of pair (p, p+1) of its lattice; the last entry of each

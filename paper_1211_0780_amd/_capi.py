@@ -14,6 +14,7 @@ XY_OK, XY_ERR_ARG, XY_ERR_ODD_L, XY_ERR_OOM, XY_ERR_HIP, XY_ERR_STATE, XY_ERR_UN
 XY_FP32, XY_FP64 = 0, 1
 XY_START_RANDOM, XY_START_ORDERED = 0, 1
 XY_F_NO_RECHECK = 0x1
+XY_F_NO_FUSED_OR = 0x2
 
 STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM", 4: "XY_ERR_HIP",
                 5: "XY_ERR_STATE", 6: "XY_ERR_UNSUPPORTED"}
@@ -21,7 +22,7 @@ STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM",
 EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange", "xy_run",
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
-           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts"]
+           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused"]
 
 
 class XYConfig(ctypes.Structure):
@@ -104,6 +105,10 @@ def lib():
         L.xy_get_bond_sums.restype = i32
         L.xy_get_swap_accepts.argtypes = [vp, i64p]
         L.xy_get_swap_accepts.restype = i32
+        L.xy_set_tiling_fused.argtypes = [vp, i32, i32, i32]
+        L.xy_set_tiling_fused.restype = i32
+        L.xy_get_tiling_fused.argtypes = [vp, i32, ip, ip]
+        L.xy_get_tiling_fused.restype = i32
         L.xy_destroy.argtypes = [vp]
         L.xy_destroy.restype = None
         _lib = L

@@ -26,6 +26,8 @@ namespace {
 
 thread_local std::string g_init_error;
 
+constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS a launch may ask for without attributes
+
 struct Tiling {
     int TY = 0, TZ = 0, spt = 0;
 };
@@ -97,7 +99,14 @@ struct xy_ctx_s {
     bool partials_are_sweep = false;
 
     std::vector<GraphEntry> graphs;
-    std::vector<Tiling> tiles;  // FP32: per-lattice tile choice
+    std::vector<Tiling> tiles;  // FP32: per-lattice tile choice of the half-sweep kernels
+    std::vector<Tiling> tiles2; // FP32: per-lattice tile choice of the fused over-relaxation
+    bool fused_or = false;      // over-relaxation substeps as one fused kernel each
+    std::vector<LatDev> lat_or2;
+    int items_or2 = 0, spt2 = 0;
+    size_t lds2 = 0;
+    LatDev *d_lat_or2 = nullptr;
+    void *ang2 = nullptr;       // second configuration buffer for the fused kernel
     std::string err;
 };
 
@@ -154,6 +163,22 @@ Tiling default_tiling(int L, int R)
     return t;
 }
 
+// Default tile of the fused over-relaxation kernel: at most two tile
+// columns per thread (its register footprint is about twice the half-sweep's).
+Tiling default_tiling2(int L)
+{
+    const int half = L / 2;
+    Tiling t;
+    for (int d : divisors(L))
+        if (d * half <= 2 * kBlock) t.TY = d;
+    if (t.TY == 0) t.TY = 1;
+    t.TZ = 1;
+    for (int d : divisors(L))
+        if (d <= 24) t.TZ = d;
+    t.spt = spt_for(t.TY * half);
+    return t;
+}
+
 xy_status sync_stream(xy_ctx c)
 {
     XY_HIP(c, hipStreamSynchronize(c->stream));
@@ -195,18 +220,56 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
     return XY_OK;
 }
 
-// Enqueue one sweep; if measure_last, the final half-sweep also produces the
-// measurement partials.
+// One fused over-relaxation substep from buffer `from` into buffer `to`.
+xy_status launch_or2(xy_ctx c, void *from, void *to, bool fuse_measure)
+{
+    SweepArgs a{};
+    a.lats = c->d_lat_or2;
+    a.n_lat = c->n_lat;
+    a.total_items = c->items_or2;
+    a.ang = from;
+    a.ang_dst = to;
+    a.beta = c->d_beta;
+    a.pos = c->d_pos;
+    a.ctl = c->d_ctl;
+    a.k0 = c->k0;
+    a.k1 = c->k1;
+    a.partials = c->d_partials;
+    a.macc = c->d_macc;
+    a.rq = c->d_rq;
+    const int grid = std::min(a.total_items, c->grid_sweep > 0 ? c->grid_sweep : a.total_items);
+    hipError_t e = launch_or2_f32(fuse_measure, c->spt2, grid, c->lds2, a, c->stream);
+    if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("fused launch: ") + hipGetErrorString(e));
+    return XY_OK;
+}
+
+// Over-relaxation substeps that run fused: all of them when n_or is even,
+// all but the last otherwise, so the configuration ends every sweep back in
+// the primary buffer (an even number of buffer swaps).
+int fused_substeps(xy_ctx c, int n_or)
+{
+    return c->fused_or ? n_or - (n_or & 1) : 0;
+}
+
+// Enqueue one sweep; if measure_last, the final kernel also produces the
+// measurement partials (in the item layout reported by partials_layout()).
 xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last)
 {
-    const int total = 2 * (n_metro + n_or);
+    const int n_fused = fused_substeps(c, n_or);
+    const int total = 2 * (n_metro + n_or - n_fused) + n_fused;
     int h = 0;
     for (int s = 0; s < n_metro; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
             xy_status st = launch_half(c, kMetro, col, s, measure_last && h == total - 1);
             if (st) return st;
         }
-    for (int s = 0; s < n_or; ++s)
+    for (int s = 0; s < n_fused; ++s, ++h) {
+        void *from = (s & 1) ? c->ang2 : c->ang;
+        void *to = (s & 1) ? c->ang : c->ang2;
+        xy_status st = launch_or2(c, from, to, measure_last && h == total - 1);
+        if (st) return st;
+    }
+    for (int s = n_fused; s < n_or; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
             xy_status st = launch_half(c, kOver, col, s, measure_last && h == total - 1);
             if (st) return st;
@@ -215,21 +278,31 @@ xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last)
     return XY_OK;
 }
 
+// Which item layout the measurement partials of a sweep come from.
+bool sweep_measures_fused(xy_ctx c, int n_or)
+{
+    const int n_fused = fused_substeps(c, n_or);
+    return n_fused > 0 && n_fused == n_or;
+}
+
 xy_status enqueue_measure_kernel(xy_ctx c)
 {
     return launch_half(c, kMeas, 1, 0, false);
 }
 
-const LatDev *meas_layout_dev(xy_ctx c, bool from_sweep)
+enum PartialsLayout { kPartMeas = 0, kPartSweep = 1, kPartOr2 = 2 };
+
+const LatDev *meas_layout_dev(xy_ctx c, int layout)
 {
     if (c->prec == XY_FP64) return c->d_lat_sweep;
-    return from_sweep ? c->d_lat_sweep : c->d_lat_meas;
+    if (layout == kPartOr2) return c->d_lat_or2;
+    return layout == kPartSweep ? c->d_lat_sweep : c->d_lat_meas;
 }
 
-xy_status enqueue_finalize(xy_ctx c, bool from_sweep_partials, double *obs, int use_ring,
-                           bool do_sum, bool do_exchange, double *bonds = nullptr)
+xy_status enqueue_finalize(xy_ctx c, int layout, double *obs, int use_ring, bool do_sum,
+                           bool do_exchange, double *bonds = nullptr)
 {
-    XY_HIP(c, launch_finalize(meas_layout_dev(c, from_sweep_partials), c->n_lat, c->max_R,
+    XY_HIP(c, launch_finalize(meas_layout_dev(c, layout), c->n_lat, c->max_R,
                               c->d_partials, c->d_beta, c->d_pos, c->d_slot_of, c->d_E, obs, bonds,
                               use_ring, (int64_t)5 * c->R_total, (int64_t)6 * c->R_total,
                               do_sum ? 1 : 0, do_exchange ? 1 : 0, c->d_sacc, c->d_ctl, c->k0, c->k1,
@@ -261,7 +334,7 @@ void free_all(xy_ctx c)
     if (c->stream || c->cap_stream) (void)hipDeviceSynchronize();
     free_graphs(c);
     if (c->own_ang && c->ang) (void)hipFree(c->ang);
-    void *ptrs[] = {c->d_lat_sweep, c->d_lat_meas, c->d_beta, c->d_pos, c->d_slot_of, c->d_ctl,
+    void *ptrs[] = {c->d_lat_or2, c->ang2, c->d_lat_sweep, c->d_lat_meas, c->d_beta, c->d_pos, c->d_slot_of, c->d_ctl,
                     c->d_partials, c->d_E, c->d_obs, c->d_bonds, c->d_macc, c->d_sacc, c->d_bad,
                     c->d_rq, c->d_rq_entries};
     for (void *p : ptrs)
@@ -371,6 +444,30 @@ void build_layout(xy_ctx c)
     }
     c->items_sweep = item_s;
     c->items_meas = item_m;
+    // fused over-relaxation layout (FP32, every lattice with L <= kBlock)
+    c->lat_or2.clear();
+    c->items_or2 = 0;
+    c->spt2 = 1;
+    c->lds2 = 0;
+    if (c->fused_or) {
+        int item2 = 0;
+        for (int l = 0; l < c->n_lat; ++l) {
+            if ((int)c->tiles2.size() <= l) c->tiles2.push_back(default_tiling2(c->L[l]));
+            const Tiling t = c->tiles2[l];
+            LatDev d = c->lat_sweep[l];
+            d.TY = t.TY;
+            d.TZ = t.TZ;
+            d.ny = d.L / t.TY;
+            d.nz = d.L / t.TZ;
+            d.items_per_slot = d.ny * d.nz;
+            d.item_base = item2;
+            item2 += d.R * d.items_per_slot;
+            c->lat_or2.push_back(d);
+            c->spt2 = std::max(c->spt2, t.spt);
+            c->lds2 = std::max(c->lds2, (size_t)(2 * (t.TY + 4) + 2 * (t.TY + 2)) * d.half * 2 * sizeof(float));
+        }
+        c->items_or2 = item2;
+    }
     c->lds_bytes = (size_t)2 * max_rowbuf * 2 * sizeof(float);  // two planes of (cos, sin)
 }
 
@@ -380,7 +477,7 @@ void build_layout(xy_ctx c)
 xy_status relayout(xy_ctx c)
 {
     build_layout(c);
-    const int n_items_max = std::max(c->items_sweep, c->items_meas);
+    const int n_items_max = std::max(std::max(c->items_sweep, c->items_meas), c->items_or2);
     if ((size_t)kPartials * n_items_max > c->partials_cap) {
         XY_HIP(c, hipStreamSynchronize(c->stream));
         (void)hipFree(c->d_partials);
@@ -393,6 +490,9 @@ xy_status relayout(xy_ctx c)
                              hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipMemcpyAsync(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat,
                              hipMemcpyHostToDevice, c->stream));
+    if (c->fused_or)
+        XY_HIP(c, hipMemcpyAsync(c->d_lat_or2, c->lat_or2.data(), sizeof(LatDev) * c->n_lat,
+                                 hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
     free_graphs(c);
     c->e_fresh = c->bonds_fresh = false;
@@ -436,6 +536,9 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     c->elem = (c->prec == XY_FP32) ? 4 : 8;
     c->n_elems = total_elems(cfg);
     c->stream = (hipStream_t)cfg->stream;
+    c->fused_or = c->prec == XY_FP32 && !(cfg->flags & XY_F_NO_FUSED_OR);
+    for (int l = 0; l < c->n_lat; ++l)
+        if (c->L[l] > kBlock) c->fused_or = false;
     build_layout(c);
 
     auto bail = [&](xy_status s) {
@@ -461,7 +564,12 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
         if ((st = dev_alloc(c, (char **)&c->ang, (size_t)c->n_elems * c->elem))) return bail(st);
         c->own_ang = true;
     }
-    const int n_items_max = std::max(c->items_sweep, c->items_meas);
+    const int n_items_max = std::max(std::max(c->items_sweep, c->items_meas), c->items_or2);
+    if (c->fused_or) {
+        if ((st = dev_alloc(c, (char **)&c->ang2, (size_t)c->n_elems * c->elem)) ||
+            (st = dev_alloc(c, &c->d_lat_or2, c->n_lat)))
+            return bail(st);
+    }
     if ((st = dev_alloc(c, &c->d_lat_sweep, c->n_lat)) || (st = dev_alloc(c, &c->d_lat_meas, c->n_lat)) ||
         (st = dev_alloc(c, &c->d_beta, c->R_total)) || (st = dev_alloc(c, &c->d_pos, c->R_total)) ||
         (st = dev_alloc(c, &c->d_slot_of, c->R_total)) || (st = dev_alloc(c, &c->d_ctl, 1)) ||
@@ -494,6 +602,8 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c->d_lat_sweep, c->lat_sweep.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
+    if (e == hipSuccess && c->fused_or)
+        e = hipMemcpy(c->d_lat_or2, c->lat_or2.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_beta, c->beta.data(), sizeof(double) * c->R_total, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_pos, ident.data(), sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_slot_of, ident.data(), sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice);
@@ -540,53 +650,63 @@ xy_status xy_sweep_profiled(xy_ctx c, int32_t n_metro, int32_t n_or, double *ms,
     if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || n_metro > 255 || n_or > 65535)
         return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
     if (c->t >= 0xffffffffull) return fail(c, XY_ERR_STATE, "sweep counter would overflow 32 bits");
-    const int n_half = 2 * (n_metro + n_or);
-    std::vector<hipEvent_t> ev(2 * n_half + 2, nullptr);
-    for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto &x : ev)
-                if (x) (void)hipEventDestroy(x);
+    const int n_fused = fused_substeps(c, n_or);
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    auto cleanup = [&]() {
+        for (auto &r : recs) {
+            if (r.a) (void)hipEventDestroy(r.a);
+            if (r.b) (void)hipEventDestroy(r.b);
+        }
+    };
+    auto timed = [&](int kind, auto &&launch) -> xy_status {
+        Rec r{kind, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+            recs.push_back(r);
             return fail(c, XY_ERR_HIP, "hipEventCreate failed");
         }
+        recs.push_back(r);
+        (void)hipEventRecord(r.a, c->stream);
+        xy_status st = launch();
+        (void)hipEventRecord(r.b, c->stream);
+        return st;
+    };
     xy_status st = XY_OK;
-    int h = 0;
     for (int s = 0; s < n_metro && !st; ++s)
-        for (int col = 0; col < 2 && !st; ++col, ++h) {
-            (void)hipEventRecord(ev[2 * h], c->stream);
-            st = launch_half(c, kMetro, col, s, false);
-            (void)hipEventRecord(ev[2 * h + 1], c->stream);
-        }
-    for (int s = 0; s < n_or && !st; ++s)
-        for (int col = 0; col < 2 && !st; ++col, ++h) {
-            (void)hipEventRecord(ev[2 * h], c->stream);
-            st = launch_half(c, kOver, col, s, false);
-            (void)hipEventRecord(ev[2 * h + 1], c->stream);
-        }
-    if (!st) {
-        (void)hipEventRecord(ev[2 * n_half], c->stream);
-        hipError_t e = launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream);
-        (void)hipEventRecord(ev[2 * n_half + 1], c->stream);
-        if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
+        for (int col = 0; col < 2 && !st; ++col)
+            st = timed(0, [&] { return launch_half(c, kMetro, col, s, false); });
+    for (int s = 0; s < n_fused && !st; ++s) {
+        void *from = (s & 1) ? c->ang2 : c->ang;
+        void *to = (s & 1) ? c->ang : c->ang2;
+        st = timed(2, [&] { return launch_or2(c, from, to, false); });
     }
+    for (int s = n_fused; s < n_or && !st; ++s)
+        for (int col = 0; col < 2 && !st; ++col)
+            st = timed(1, [&] { return launch_half(c, kOver, col, s, false); });
+    if (!st)
+        st = timed(3, [&]() -> xy_status {
+            hipError_t e = launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream);
+            return e == hipSuccess ? XY_OK : fail(c, XY_ERR_HIP, "tick launch failed");
+        });
     if (!st && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, XY_ERR_HIP, "sync failed");
     if (!st) {
-        ms[0] = ms[1] = ms[2] = 0.0;
-        launches[0] = launches[1] = launches[2] = 0;
-        for (int i = 0; i < n_half; ++i) {
-            float t = 0.f;
-            (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
-            const int kind = i < 2 * n_metro ? 0 : 1;
-            ms[kind] += t;
-            launches[kind] += 1;
+        for (int k = 0; k < 4; ++k) {
+            ms[k] = 0.0;
+            launches[k] = 0;
         }
-        float t = 0.f;
-        (void)hipEventElapsedTime(&t, ev[2 * n_half], ev[2 * n_half + 1]);
-        ms[2] = t;
-        launches[2] = 1;
+        for (auto &r : recs) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, r.a, r.b);
+            ms[r.kind] += t;
+            launches[r.kind] += 1;
+        }
         c->t += 1;
         c->e_fresh = c->bonds_fresh = false;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    cleanup();
     return st;
 }
 
@@ -597,7 +717,7 @@ xy_status xy_measure(xy_ctx c, double *obs, int32_t obs_on_device)
     xy_status st = enqueue_measure_kernel(c);
     if (st) return st;
     double *dst = obs_on_device ? obs : c->d_obs;
-    if ((st = enqueue_finalize(c, false, dst, 0, true, false, c->d_bonds))) return st;
+    if ((st = enqueue_finalize(c, kPartMeas, dst, 0, true, false, c->d_bonds))) return st;
     c->e_fresh = true;
     c->bonds_fresh = true;
     if (!obs_on_device) {
@@ -615,11 +735,11 @@ xy_status xy_exchange(xy_ctx c, int64_t *n_acc)
     xy_status st;
     if (!c->e_fresh) {
         if ((st = enqueue_measure_kernel(c))) return st;
-        if ((st = enqueue_finalize(c, false, nullptr, 0, true, false, c->d_bonds))) return st;
+        if ((st = enqueue_finalize(c, kPartMeas, nullptr, 0, true, false, c->d_bonds))) return st;
         c->e_fresh = true;
         c->bonds_fresh = true;
     }
-    if ((st = enqueue_finalize(c, false, nullptr, 0, false, true))) return st;
+    if ((st = enqueue_finalize(c, kPartMeas, nullptr, 0, false, true))) return st;
     XY_HIP(c, launch_tick(c->d_ctl, 0u, 1u, 0u, 0, c->stream));
     c->tau += 1;
     if (n_acc) {
@@ -663,7 +783,9 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         c->stream = c->cap_stream;
         XY_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         xy_status st = enqueue_sweep(c, n_metro, n_or, true);
-        if (!st) st = enqueue_finalize(c, true, obs_dev, 1, true, exch != 0, bonds_dev);
+        if (!st)
+            st = enqueue_finalize(c, sweep_measures_fused(c, n_or) ? kPartOr2 : kPartSweep, obs_dev, 1, true,
+                                  exch != 0, bonds_dev);
         if (!st) {
             hipError_t e = launch_tick(c->d_ctl, 0u, exch ? 1u : 0u, (obs_dev || bonds_dev) ? 1u : 0u, 0,
                                        c->cap_stream);
@@ -825,6 +947,72 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
     if (hipMemcpyAsync(c->d_macc, save_acc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToDevice,
                        c->stream) != hipSuccess && !st)
         st = fail(c, XY_ERR_HIP, "restoring counters failed");
+    // Fused over-relaxation tiles: the kernel reads the configuration and
+    // writes the second buffer only, so timing it leaves the chain untouched.
+    if (!st && c->fused_or && n_or >= 2) {
+        for (int l = 0; l < c->n_lat && !st; ++l) {
+            const LatDev &base = c->lat_sweep[l];
+            const int L = base.L, half = base.half;
+            Tiling best = c->tiles2[l];
+            double best_ms = 1e300;
+            for (int ty : divisors(L)) {
+                if (ty * half > 4 * kBlock) continue;
+                if (ty * half < kBlock / 2 && ty != L) continue;
+                for (int tz : divisors(L)) {
+                    if (tz < 2 && L > 2) continue;
+                    if (tz > 64 && tz != L) continue;
+                    Tiling t;
+                    t.TY = ty;
+                    t.TZ = tz;
+                    t.spt = spt_for(ty * half);
+                    LatDev one = base;
+                    one.TY = ty;
+                    one.TZ = tz;
+                    one.ny = L / ty;
+                    one.nz = L / tz;
+                    one.items_per_slot = one.ny * one.nz;
+                    one.item_base = 0;
+                    const int items = one.R * one.items_per_slot;
+                    if (hipMemcpyAsync(d_one, &one, sizeof(LatDev), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+                        st = fail(c, XY_ERR_HIP, "upload failed");
+                        break;
+                    }
+                    SweepArgs a{};
+                    a.lats = d_one;
+                    a.n_lat = 1;
+                    a.total_items = items;
+                    a.ang = c->ang;
+                    a.ang_dst = c->ang2;
+                    a.beta = c->d_beta;
+                    a.pos = c->d_pos;
+                    a.ctl = c->d_ctl;
+                    a.partials = c->d_partials;
+                    a.macc = c->d_macc;
+                    a.rq = c->d_rq;
+                    const size_t lds = (size_t)(2 * (ty + 4) + 2 * (ty + 2)) * half * 2 * sizeof(float);
+                    if (lds > kMaxLds) continue;
+                    hipError_t e = launch_or2_f32(false, t.spt, items, lds, a, c->stream);
+                    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r)
+                        e = launch_or2_f32(false, t.spt, items, lds, a, c->stream);
+                    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        st = fail(c, XY_ERR_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = t;
+                    }
+                }
+                if (st) break;
+            }
+            if (!st) c->tiles2[l] = best;
+        }
+    }
     (void)hipStreamSynchronize(c->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -854,6 +1042,34 @@ xy_status xy_set_tiling(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz, int32
     return relayout(c);
 }
 
+xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!c->fused_or) return fail(c, XY_ERR_UNSUPPORTED, "this context does not use the fused over-relaxation");
+    if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
+    const int L = c->L[lattice];
+    if (ty < 1 || tz < 1 || L % ty != 0 || L % tz != 0)
+        return fail(c, XY_ERR_ARG, "ty and tz must divide L");
+    if (ty * (L / 2) > 8 * kBlock) return fail(c, XY_ERR_ARG, "ty * L/2 must be <= 2048");
+    if ((size_t)(4 * ty + 12) * (L / 2) * 2 * sizeof(float) > kMaxLds)
+        return fail(c, XY_ERR_ARG, "tile needs more than 64 KiB of LDS");
+    Tiling t;
+    t.TY = ty;
+    t.TZ = tz;
+    t.spt = spt_for(ty * (L / 2));
+    c->tiles2[lattice] = t;
+    return relayout(c);
+}
+
+xy_status xy_get_tiling_fused(xy_ctx c, int32_t lattice, int32_t *ty, int32_t *tz)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
+    if (ty) *ty = c->fused_or ? c->tiles2[lattice].TY : 0;
+    if (tz) *tz = c->fused_or ? c->tiles2[lattice].TZ : 0;
+    return XY_OK;
+}
+
 xy_status xy_get_tiling(xy_ctx c, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
@@ -876,7 +1092,7 @@ xy_status xy_get_bond_sums(xy_ctx c, double *out, int32_t out_on_device)
     if (!out) return fail(c, XY_ERR_ARG, "out is NULL");
     if (!c->bonds_fresh) {
         xy_status st = enqueue_measure_kernel(c);
-        if (!st) st = enqueue_finalize(c, false, nullptr, 0, true, false, c->d_bonds);
+        if (!st) st = enqueue_finalize(c, kPartMeas, nullptr, 0, true, false, c->d_bonds);
         if (st) return st;
         c->e_fresh = true;
         c->bonds_fresh = true;

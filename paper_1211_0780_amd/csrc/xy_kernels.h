@@ -58,6 +58,7 @@ struct SweepArgs {
     int32_t n_lat;
     int32_t total_items;
     void *ang;                 // float* (FP32, turns) or double* (FP64, radians)
+    void *ang_dst;             // fused over-relaxation: where the new configuration goes
     const double *beta;        // [R_total] by position index
     const int32_t *pos;        // [R_total] beta-position held by each storage slot
     const Ctl *ctl;
@@ -73,6 +74,8 @@ struct SweepArgs {
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid,
                            size_t lds_bytes, const SweepArgs &a, hipStream_t s);
+hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
+                          hipStream_t s);
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
                           int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);

@@ -409,6 +409,251 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Fused over-relaxation substep: colour 0 then colour 1 of one substep in a
+// single streaming pass, reading the old configuration from `ang` and
+// writing the new one to `ang_dst` (ping-pong buffers, so no tile ever reads
+// a value another tile has already replaced).
+//
+// At step z the kernel updates colour 0 at plane z ("a") and colour 1 at
+// plane z-1 ("b"); b needs colour 0 already updated at planes z-2, z-1, z,
+// which a has produced by then, so the pass is the sequential order of the
+// two half-sweeps.  Colour 0 is also updated, redundantly and without being
+// stored, on the halo rows y0-1, y0+TY and the halo planes z0-1, z0+TZ: the
+// same deterministic arithmetic on the same inputs as the tile that owns
+// them, so colour 1 at the tile edge sees exactly the values that tile
+// writes.  That needs the old colour 1 two rows and two planes out.
+//
+// Per thread: SPT tile columns ("T", rows y0..y0+TY-1), one halo column
+// ("H", rows y0-1 or y0+TY) and one outer column ("O", rows y0-2 or
+// y0+TY+1, old colour 1 only); H and O need 2*(L/2) <= kBlock, so L <= 256.
+// LDS: P1 = old colour 1 (cos, sin) of plane z on rows y0-2..y0+TY+1 and
+// P0 = new colour 0 of plane z on rows y0-1..y0+TY, both double-buffered.
+// Loads run two planes ahead in alternating register sets, as in
+// k_tile_f32.  MEAS adds the measurement of the new configuration to b
+// (this substep must then be the last of the sweep).
+// ---------------------------------------------------------------------------
+template <bool MEAS, int SPT>
+__global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
+{
+    extern __shared__ f2 lds[];
+    const int tid = threadIdx.x;
+
+    for (int v = blockIdx.x; v < a.total_items; v += gridDim.x) {
+        const int w = xcd_item(v, a.total_items);
+        const int li = uni(find_lattice(a.lats, a.n_lat, w));
+        const LatDev d = load_lat_uniform(a.lats + li);
+        const int L = d.L, half = d.half, TY = d.TY, TZ = d.TZ;
+        const int wl = w - d.item_base;
+        const int slot = wl / d.items_per_slot;
+        const int rem = wl - slot * d.items_per_slot;
+        const int ty = rem % d.ny, tz = rem / d.ny;
+        const int y0 = ty * TY, z0 = tz * TZ;
+        const uint32_t plane_b = (uint32_t)L * (uint32_t)half * 4u;
+        const int64_t nh = d.N / 2;
+        const float *src = (const float *)a.ang + d.base + (int64_t)slot * d.N;
+        float *dst = (float *)a.ang_dst + d.base + (int64_t)slot * d.N;
+        const __amdgpu_buffer_rsrc_t r0s = colour_rsrc(src, nh);
+        const __amdgpu_buffer_rsrc_t r1s = colour_rsrc(src + nh, nh);
+        const __amdgpu_buffer_rsrc_t r0d = colour_rsrc(dst, nh);
+        const __amdgpu_buffer_rsrc_t r1d = colour_rsrc(dst + nh, nh);
+        const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(src, 0);
+        const int rows1 = TY + 4, rows0 = TY + 2;
+        f2 *P1[2] = {lds, lds + rows1 * half};
+        f2 *P0[2] = {lds + 2 * rows1 * half, lds + 2 * rows1 * half + rows0 * half};
+        auto wrapy = [L](int y) { return y < 0 ? y + L : (y >= L ? y - L : y); };
+        auto wrapz = wrapy;
+        auto xm = [half](int j) { return j == 0 ? half - 1 : j - 1; };
+        auto xp = [half](int j) { return j + 1 == half ? 0 : j + 1; };
+
+        // ---- slot geometry (constant over z) ----
+        uint32_t voffT[SPT];
+        int l1T[SPT], l0T[SPT], l1xe[SPT], l1xo[SPT], l0xe[SPT], l0xo[SPT];
+        bool okT[SPT], pz0[SPT];
+        const int zs = wrapz(z0 - 1);  // first step's plane
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            const int f = tid + s * kBlock;
+            okT[s] = f < TY * half;
+            const int fl = okT[s] ? f : 0;
+            const int yl = fl / half, j = fl - yl * half, y = y0 + yl;
+            voffT[s] = (uint32_t)(y * half + j) * 4u;
+            l1T[s] = (yl + 2) * half + j;
+            l0T[s] = (yl + 1) * half + j;
+            // x-neighbour on the first step (plane zs) and on the next: for
+            // colour 0 at (y, z) and colour 1 at (y, z-1) alike it is j+1
+            // when (y + z) is odd, j-1 when even
+            const bool podd = ((y + zs) & 1) != 0;
+            pz0[s] = podd;
+            l1xe[s] = (yl + 2) * half + (podd ? xp(j) : xm(j));
+            l1xo[s] = (yl + 2) * half + (podd ? xm(j) : xp(j));
+            l0xe[s] = (yl + 1) * half + (podd ? xp(j) : xm(j));
+            l0xo[s] = (yl + 1) * half + (podd ? xm(j) : xp(j));
+        }
+        const bool okH = tid < 2 * half;
+        const int eH = okH ? tid : 0;
+        const int rH = eH >= half, jH = eH - rH * half;
+        const int yH = rH ? wrapy(y0 + TY) : wrapy(y0 - 1);
+        const uint32_t voffH = (uint32_t)(yH * half + jH) * 4u;
+        const int l1H = (rH ? TY + 2 : 1) * half + jH;
+        const int l0H = (rH ? TY + 1 : 0) * half + jH;
+        const bool poddH = ((yH + zs) & 1) != 0;
+        const int l1Hxe = (rH ? TY + 2 : 1) * half + (poddH ? xp(jH) : xm(jH));
+        const int l1Hxo = (rH ? TY + 2 : 1) * half + (poddH ? xm(jH) : xp(jH));
+        const int yO = rH ? wrapy(y0 + TY + 1) : wrapy(y0 - 2);
+        const uint32_t voffO = (uint32_t)(yO * half + jH) * 4u;
+        const int l1O = (rH ? TY + 3 : 0) * half + jH;
+
+        // ---- prologue: state for the first step (plane zs = z0-1) ----
+        auto pb = [&](int z) { return (uint32_t)wrapz(z) * plane_b; };
+        f2 c1m[SPT], c1c[SPT], c1p[SPT], c0n1[SPT], c0n2[SPT];
+        float r1m[SPT], r1c[SPT], r1p[SPT], t0[SPT];
+        float aT1[SPT], aT0[SPT], bT1[SPT], bT0[SPT];
+        f2 hm, hc, hp;
+        float ht0, aH1, aH0, bH1, bH0, aO, bO;
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            r1m[s] = bload(r1s, voffT[s], pb(z0 - 2));
+            r1c[s] = bload(r1s, voffT[s], pb(z0 - 1));
+            r1p[s] = bload(r1s, voffT[s], pb(z0));
+            t0[s] = bload(r0s, voffT[s], pb(z0 - 1));
+            aT1[s] = bload(r1s, voffT[s], pb(z0 + 1));
+            aT0[s] = bload(r0s, voffT[s], pb(z0));
+            c1m[s] = sincos_turns(r1m[s]);
+            c1c[s] = sincos_turns(r1c[s]);
+            c1p[s] = sincos_turns(r1p[s]);
+            c0n1[s] = f2{0.f, 0.f};
+            c0n2[s] = f2{0.f, 0.f};
+            P1[0][l1T[s]] = c1c[s];
+        }
+        hm = sincos_turns(bload(r1s, voffH, pb(z0 - 2)));
+        hc = sincos_turns(bload(r1s, voffH, pb(z0 - 1)));
+        hp = sincos_turns(bload(r1s, voffH, pb(z0)));
+        ht0 = bload(r0s, voffH, pb(z0 - 1));
+        aH1 = bload(r1s, voffH, pb(z0 + 1));
+        aH0 = bload(r0s, voffH, pb(z0));
+        const f2 o0 = sincos_turns(bload(r1s, voffO, pb(z0 - 1)));
+        aO = bload(r1s, voffO, pb(z0));
+        if (okH) {
+            P1[0][l1H] = hc;
+            P1[0][l1O] = o0;
+        }
+        lds_barrier();
+
+        double acc[kPartials];
+#pragma unroll
+        for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
+
+        // ---- one step: a at plane z = z0-1+zz, b at plane z-1 ----
+        auto step = [&](const int zz, const int par, float (&preT1)[SPT], float (&preT0)[SPT],
+                        float &preH1, float &preH0, float &preO, float (&nxtT1)[SPT],
+                        float (&nxtT0)[SPT], float &nxtH1, float &nxtH0, float &nxtO) {
+            const int z = z0 - 1 + zz;
+            const f2 *p1 = P1[par];
+            f2 *p0w = P0[par];
+            const f2 *p0r = P0[par ^ 1];
+            f2 *p1n = P1[par ^ 1];
+            {
+                // last planes needed: old colour 1 at z0+TZ+1 (z neighbour of
+                // a at z0+TZ), old colour 0 and the outer rows at z0+TZ; all
+                // are issued at step TZ-1
+                const bool need = zz <= TZ - 1;
+                const __amdgpu_buffer_rsrc_t q1 = need ? r1s : rnull;
+                const __amdgpu_buffer_rsrc_t q2 = q1;
+                const __amdgpu_buffer_rsrc_t q0 = need ? r0s : rnull;
+#pragma unroll
+                for (int s = 0; s < SPT; ++s) {
+                    nxtT1[s] = bload(q1, voffT[s], pb(z + 3));
+                    nxtT0[s] = bload(q0, voffT[s], pb(z + 2));
+                }
+                nxtH1 = bload(q1, voffH, pb(z + 3));
+                nxtH0 = bload(q0, voffH, pb(z + 2));
+                nxtO = bload(q2, voffO, pb(z + 2));
+            }
+            const bool store_a = zz >= 1 && zz <= TZ;
+            const uint32_t sz = pb(z), szm = pb(z - 1);
+            // a: colour 0 at plane z on tile and halo columns
+            f2 c0cur[SPT];
+#pragma unroll
+            for (int s = 0; s < SPT; ++s) {
+                const int lx = par ? l1xo[s] : l1xe[s];
+                const f2 n1 = p1[l1T[s] - half], n2 = p1[l1T[s] + half], n3 = p1[l1T[s]], n4 = p1[lx];
+                const float hx = ((c1m[s].c + c1p[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
+                const float hy = ((c1m[s].s + c1p[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
+                const float nv = overrelax_turns(t0[s], hx, hy);
+                if (store_a && okT[s]) bstore(nv, r0d, voffT[s], sz);
+                c0cur[s] = sincos_turns(nv);
+                p0w[l0T[s]] = c0cur[s];
+            }
+            {
+                const int lx = par ? l1Hxo : l1Hxe;
+                const f2 n1 = p1[l1H - half], n2 = p1[l1H + half], n3 = p1[l1H], n4 = p1[lx];
+                const float hx = ((hm.c + hp.c) + (n1.c + n2.c)) + (n3.c + n4.c);
+                const float hy = ((hm.s + hp.s) + (n1.s + n2.s)) + (n3.s + n4.s);
+                const f2 hv = sincos_turns(overrelax_turns(ht0, hx, hy));
+                if (okH) p0w[l0H] = hv;
+            }
+            // b: colour 1 at plane z-1 on tile columns (from the third step on)
+            if (zz >= 2) {
+#pragma unroll
+                for (int s = 0; s < SPT; ++s) {
+                    const int lx = par ? l0xo[s] : l0xe[s];
+                    const f2 m1 = p0r[l0T[s] - half], m2 = p0r[l0T[s] + half], m3 = p0r[l0T[s]],
+                             m4 = p0r[lx];
+                    const float hx = ((c0n2[s].c + c0cur[s].c) + (m1.c + m2.c)) + (m3.c + m4.c);
+                    const float hy = ((c0n2[s].s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
+                    const float nv = overrelax_turns(r1m[s], hx, hy);
+                    if (okT[s]) bstore(nv, r1d, voffT[s], szm);
+                    if constexpr (MEAS) {
+                        if (okT[s]) {
+                            // colour 1 at (y, z-1) has x = 2j + p, p = (y + z) & 1
+                            // (L even keeps the parity through the z wrap); the
+                            // same-j neighbour is +x when p = 0, -x when p = 1
+                            const bool podd = pz0[s] != (par != 0);
+                            const f2 xpv = podd ? m4 : m3, xmv = podd ? m3 : m4;
+                            const f2 sc = sincos_turns(nv);
+                            const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0n2[s].c};
+                            const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0n2[s].s};
+                            measure_site(acc, sc.c, sc.s, c0n1[s].c, c0n1[s].s, nc, ns);
+                        }
+                    }
+                }
+            }
+            // next plane of old colour 1 into LDS; shift the z windows
+#pragma unroll
+            for (int s = 0; s < SPT; ++s) {
+                p1n[l1T[s]] = c1p[s];
+                c0n2[s] = c0n1[s];
+                c0n1[s] = c0cur[s];
+                c1m[s] = c1c[s];
+                c1c[s] = c1p[s];
+                c1p[s] = sincos_turns(preT1[s]);
+                r1m[s] = r1c[s];
+                r1c[s] = r1p[s];
+                r1p[s] = preT1[s];
+                t0[s] = preT0[s];
+            }
+            const f2 onext = sincos_turns(preO);
+            if (okH) {
+                p1n[l1H] = hp;
+                p1n[l1O] = onext;
+            }
+            hm = hc;
+            hc = hp;
+            hp = sincos_turns(preH1);
+            ht0 = preH0;
+            lds_barrier();
+        };
+
+        const int steps = TZ + 2;
+        for (int zz = 0; zz < steps; zz += 2) {
+            step(zz, 0, aT1, aT0, aH1, aH0, aO, bT1, bT0, bH1, bH0, bO);
+            if (zz + 1 < steps) step(zz + 1, 1, bT1, bT0, bH1, bH0, bO, aT1, aT0, aH1, aH0, aO);
+        }
+        if constexpr (MEAS) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Re-take the queued near-threshold Metropolis decisions in float64: the six
 // neighbour angles (other colour, untouched by this half-sweep) are read
 // again, dE and exp(-beta dE) evaluated in double, and the site is corrected
@@ -737,6 +982,28 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int g
     if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, spt, grid, lds, a, s);
     if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, spt, grid, lds, a, s);
     return hipErrorInvalidValue;
+}
+
+template <bool MEAS>
+static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s)
+{
+    switch (spt) {
+    case 1: hipLaunchKernelGGL((k_or2_f32<MEAS, 1>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_or2_f32<MEAS, 2>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_or2_f32<MEAS, 3>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_or2_f32<MEAS, 4>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((k_or2_f32<MEAS, 5>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 6: hipLaunchKernelGGL((k_or2_f32<MEAS, 6>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_or2_f32<MEAS, 8>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds, const SweepArgs &a,
+                          hipStream_t s)
+{
+    return fuse_measure ? launch_or2_spt<true>(spt, grid, lds, a, s) : launch_or2_spt<false>(spt, grid, lds, a, s);
 }
 
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,

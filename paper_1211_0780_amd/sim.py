@@ -27,7 +27,7 @@ class Sim:
     """
 
     def __init__(self, L, betas, seed=1, prec="fp32", start="random", recheck=True,
-                 stream=None, device=None):
+                 fused_or=True, stream=None, device=None):
         import torch
         self.L = [int(v) for v in (L if isinstance(L, (list, tuple)) else [L])]
         if betas and np.ndim(betas[0]) == 0:
@@ -53,7 +53,7 @@ class Sim:
         cfg.seed = self.seed
         cfg.prec = self.prec
         cfg.start = {"random": C.XY_START_RANDOM, "ordered": C.XY_START_ORDERED}[start]
-        cfg.flags = 0 if recheck else C.XY_F_NO_RECHECK
+        cfg.flags = (0 if recheck else C.XY_F_NO_RECHECK) | (0 if fused_or else C.XY_F_NO_FUSED_OR)
         nbytes = C.lib().xy_angles_bytes(ctypes.byref(cfg))
         if nbytes == 0:
             C.check(C.lib().xy_init(ctypes.byref(cfg), ctypes.byref(ctypes.c_void_p())))
@@ -111,12 +111,13 @@ class Sim:
         return out
 
     def sweep_profiled(self, n_metro=1, n_or=1):
-        """xy_sweep with per-kernel HIP-event timing: returns
-        ({'metro': ms, 'over': ms, 'other': ms}, {'metro': n, 'over': n, 'other': n})."""
-        ms = (ctypes.c_double * 3)()
-        n = (ctypes.c_int32 * 3)()
+        """xy_sweep with per-kernel HIP-event timing: returns summed milliseconds
+        and launch counts keyed 'metro', 'over' (half-sweeps), 'over_fused'
+        (fused substeps) and 'other'."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int32 * 4)()
         C.check(C.lib().xy_sweep_profiled(self._ctx, int(n_metro), int(n_or), ms, n), self._ctx)
-        keys = ("metro", "over", "other")
+        keys = ("metro", "over", "over_fused", "other")
         return dict(zip(keys, list(ms))), dict(zip(keys, list(n)))
 
     def autotune(self, n_metro=1, n_or=1, reps=3):
@@ -127,6 +128,14 @@ class Sim:
 
     def set_tiling(self, lattice, ty, tz, grid_cap=0):
         C.check(C.lib().xy_set_tiling(self._ctx, int(lattice), int(ty), int(tz), int(grid_cap)), self._ctx)
+
+    def set_tiling_fused(self, lattice, ty, tz):
+        C.check(C.lib().xy_set_tiling_fused(self._ctx, int(lattice), int(ty), int(tz)), self._ctx)
+
+    def get_tiling_fused(self, lattice=0):
+        ty, tz = ctypes.c_int32(), ctypes.c_int32()
+        C.check(C.lib().xy_get_tiling_fused(self._ctx, int(lattice), ctypes.byref(ty), ctypes.byref(tz)), self._ctx)
+        return ty.value, tz.value
 
     def get_tiling(self, lattice=0):
         ty, tz, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

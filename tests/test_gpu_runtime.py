@@ -149,3 +149,47 @@ def test_autotune_leaves_the_chain_untouched(gpu):
     a.run(3, 1, 2, exchange_every=1)
     b.run(3, 1, 2, exchange_every=1)
     assert np.array_equal(gpu_states(a), gpu_states(b))
+
+
+@pytest.mark.parametrize("L,betas,tiles", [
+    (16, [0.44, 0.46], None),
+    (24, [0.40, 0.45, 0.50], (4, 3)),
+    (12, [0.45], (12, 12)),          # one tile per slot: halo rows and planes wrap onto the tile
+    (10, [0.3, 0.5], (2, 5)),
+    (160, [0.4542], (5, 20)),        # the benchmark lattice
+])
+def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
+    """The fused substep performs the same float32 operations in the same
+    order as the colour-0 and colour-1 half-sweep kernels (which are checked
+    against the oracle site by site), so the configurations are bit-identical."""
+    from paper_1211_0780_amd.sim import Sim
+    a = Sim(L, [betas], seed=19, prec="fp32", fused_or=True)
+    b = Sim(L, [betas], seed=19, prec="fp32", fused_or=False)
+    if tiles:
+        a.set_tiling_fused(0, *tiles)
+    for sweep in range(3):
+        a.sweep(1, 4)
+        b.sweep(1, 4)
+        assert np.array_equal(gpu_states(a), gpu_states(b)), sweep
+    a.sweep(0, 3)   # odd count: two fused substeps and one pair of half-sweeps
+    b.sweep(0, 3)
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+
+
+def test_fused_measurement_equals_half_sweep_measurement(gpu):
+    from paper_1211_0780_amd.sim import Sim
+    betas = list(np.linspace(0.44, 0.46, 4))
+    a = Sim(16, [betas], seed=4, prec="fp32", fused_or=True)
+    b = Sim(16, [betas], seed=4, prec="fp32", fused_or=False)
+    n = 5
+    oa = torch.zeros((n, 4, 5), dtype=torch.float64, device=gpu)
+    ob = torch.zeros((n, 4, 5), dtype=torch.float64, device=gpu)
+    ba = torch.zeros((n, 4, 6), dtype=torch.float64, device=gpu)
+    bb = torch.zeros((n, 4, 6), dtype=torch.float64, device=gpu)
+    a.run(n, 1, 4, exchange_every=1, obs=oa, bonds=ba)
+    b.run(n, 1, 4, exchange_every=1, obs=ob, bonds=bb)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.permutation() == b.permutation()
+    assert np.allclose(oa.cpu().numpy(), ob.cpu().numpy(), rtol=1e-12, atol=1e-9)
+    assert np.allclose(ba.cpu().numpy(), bb.cpu().numpy(), rtol=1e-12, atol=1e-9)
