@@ -38,7 +38,7 @@ L, R, SEED = 160, 32, 4
 BETA_LO, BETA_HI = 0.4538, 0.4546
 N_METRO, N_OR = 1, 10
 DEFAULT_TILING = "8x20"
-DEFAULT_TILING_FUSED = "5x20"
+DEFAULT_TILING_FUSED = "8x40"
 
 
 def _oracle_one_sweep(args):

@@ -197,6 +197,15 @@ xy_status xy_run_ex(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
  * when the state changed since the last measurement. */
 xy_status xy_get_bond_sums(xy_ctx ctx, double *out, int32_t out_on_device);
 
+/*
+ * Metropolis proposal: window = 0 (the default) proposes theta' = 2*pi*U(r0)
+ * uniformly on the circle; 0 < window <= 2*pi proposes the symmetric
+ * restricted move theta' = theta + window*(U(r0) - 1/2), wrapped into
+ * [0, 2pi).  The paper does not state its proposal (Sec. II); the window
+ * raises acceptance at large beta.  Applies to later sweeps.
+ */
+xy_status xy_set_proposal_window(xy_ctx ctx, double window);
+
 /* Copy the N_l angles (radians in [0, 2pi), natural site order) of the
  * configuration at (lattice, beta_pos) to host memory.  Waits. */
 xy_status xy_get_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *host);

@@ -53,15 +53,16 @@ def lib():
         L.orc_uniform.restype = c_dbl
         L.orc_init.argtypes = [dp, c_int, c_int, c_int, c_u64]
         L.orc_init.restype = None
-        L.orc_metro_half.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_int]
+        L.orc_metro_half.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_dbl, c_int]
         L.orc_metro_half.restype = ctypes.c_int64
-        L.orc_metro_site.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, ctypes.c_int64]
+        L.orc_metro_site.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_dbl,
+                                     ctypes.c_int64]
         L.orc_metro_site.restype = c_int
         L.orc_or_site.argtypes = [dp, c_int, ctypes.c_int64]
         L.orc_or_site.restype = None
         L.orc_or_half.argtypes = [dp, c_int, c_int]
         L.orc_or_half.restype = None
-        L.orc_sweep.argtypes = [dp, c_int, c_int, dp, c_u64, c_u32, c_int, c_int, c_int, i64p]
+        L.orc_sweep.argtypes = [dp, c_int, c_int, dp, c_u64, c_u32, c_int, c_int, c_int, c_dbl, i64p]
         L.orc_sweep.restype = None
         L.orc_measure.argtypes = [dp, c_int, dp]
         L.orc_measure.restype = None
@@ -70,7 +71,7 @@ def lib():
         L.orc_exchange.argtypes = [dp, dp, c_int, c_int, dp, c_u64, c_u32, c_int, i64p]
         L.orc_exchange.restype = c_int
         L.orc_run.argtypes = [dp, c_int, c_int, dp, c_u64, c_int, c_int, c_u32, c_u32, c_int,
-                              c_int, c_int, c_int, dp, i64p, i64p]
+                              c_int, c_int, c_dbl, c_int, dp, i64p, i64p]
         L.orc_run.restype = None
         _lib = L
     return _lib
@@ -108,16 +109,19 @@ def init(L, R, seed, lat=0):
     return th
 
 
-def metro_half(theta, L, beta, seed, t, lat, k, substep, colour):
-    """In place on one configuration (float64 array of N).  Returns accepts."""
+def metro_half(theta, L, beta, seed, t, lat, k, substep, colour, window=0.0):
+    """In place on one configuration (float64 array of N).  Returns accepts.
+    window = 0: uniform proposal; window w > 0: theta + w (U - 1/2)."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
-    return lib().orc_metro_half(_dp(theta), L, float(beta), seed, t, lat, k, substep, colour)
+    return lib().orc_metro_half(_dp(theta), L, float(beta), seed, t, lat, k, substep, float(window),
+                                colour)
 
 
-def metro_site(theta, L, beta, seed, t, lat, k, substep, i):
+def metro_site(theta, L, beta, seed, t, lat, k, substep, i, window=0.0):
     """Metropolis update of site i alone (in place); returns 1 if accepted."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
-    return lib().orc_metro_site(_dp(theta), L, float(beta), seed, t, lat, k, substep, int(i))
+    return lib().orc_metro_site(_dp(theta), L, float(beta), seed, t, lat, k, substep, float(window),
+                                int(i))
 
 
 def or_site(theta, L, i):
@@ -131,13 +135,13 @@ def or_half(theta, L, colour):
     lib().orc_or_half(_dp(theta), L, colour)
 
 
-def sweep(theta, L, beta, seed, t, lat, n_metro, n_or):
+def sweep(theta, L, beta, seed, t, lat, n_metro, n_or, window=0.0):
     """In place on (R, N) configurations by beta-position.  Returns accepts per k."""
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     R = beta.size
     assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == R * L ** 3
     acc = np.zeros(R, dtype=np.int64)
-    lib().orc_sweep(_dp(theta), L, R, _dp(beta), seed, t, lat, n_metro, n_or, _i64p(acc))
+    lib().orc_sweep(_dp(theta), L, R, _dp(beta), seed, t, lat, n_metro, n_or, float(window), _i64p(acc))
     return acc
 
 
@@ -167,7 +171,7 @@ def exchange(theta, E, L, beta, seed, tau, lat=0, n_acc=None):
 
 
 def run(L, beta, seed, n_sweeps, n_metro, n_or, exchange_every=1, lat=0, ordered=False,
-        t0=0, tau0=0):
+        t0=0, tau0=0, window=0.0):
     """A whole run; returns (theta (R,N), obs (n_sweeps,R,5), metro accepts (R,),
     swap accepts (R,))."""
     beta = np.ascontiguousarray(beta, dtype=np.float64)
@@ -177,5 +181,5 @@ def run(L, beta, seed, n_sweeps, n_metro, n_or, exchange_every=1, lat=0, ordered
     macc = np.zeros(R, dtype=np.int64)
     sacc = np.zeros(R, dtype=np.int64)
     lib().orc_run(_dp(th), L, R, _dp(beta), seed, lat, int(ordered), t0, tau0, n_sweeps,
-                  n_metro, n_or, exchange_every, _dp(obs), _i64p(macc), _i64p(sacc))
+                  n_metro, n_or, float(window), exchange_every, _dp(obs), _i64p(macc), _i64p(sacc))
     return th, obs, macc, sacc

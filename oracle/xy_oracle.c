@@ -122,14 +122,15 @@ void orc_init(double *theta, int L, int R, int lat, uint64_t seed)
  * white sites), which applies it to every site of that colour in increasing
  * i.  With
  * r = Philox(i, t, (lat << 16) | k, (METRO << 24) | substep):
- *     proposal   theta' = 2*pi*U(r0)        (uniform on the circle)
+ *     proposal   theta' = 2*pi*U(r0)        (uniform on the circle), or, with a
+ *                window w > 0, theta' = wrap(theta + w (U(r0) - 1/2)) (symmetric)
  *     dE         = H(theta') - H(theta), evaluated from Eq. (1) over the six
  *                  bonds of site i:  sum_j [cos(theta - theta_j) - cos(theta' - theta_j)]
  *     accept iff U(r1) < exp(-beta * dE)
  * The site update returns 1 if accepted; the half-sweep returns the count.
  * ------------------------------------------------------------------------ */
 int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
-                   int k, int substep, int64_t i)
+                   int k, int substep, double window, int64_t i)
 {
     int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
     int64_t nb[6];
@@ -137,7 +138,8 @@ int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t,
     uint32_t r[4];
     draw(seed, (uint32_t)i, t, (uint32_t)lat, (uint32_t)k, ORC_PHASE_METRO, (uint32_t)substep, r);
     double th_old = theta[i];
-    double th_new = TWO_PI * orc_uniform(r[0]);
+    double th_new = window > 0.0 ? wrap_angle(th_old + window * (orc_uniform(r[0]) - 0.5))
+                                 : TWO_PI * orc_uniform(r[0]);
     double u = orc_uniform(r[1]);
     double dE = 0.0;
     for (int n = 0; n < 6; ++n) {
@@ -152,7 +154,7 @@ int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t,
 }
 
 int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_t t,
-                       int lat, int k, int substep, int colour)
+                       int lat, int k, int substep, double window, int colour)
 {
     int64_t accepted = 0;
     for (int z = 0; z < L; ++z)
@@ -160,7 +162,7 @@ int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_
             for (int x = 0; x < L; ++x) {
                 if (((x + y + z) & 1) != colour) continue;
                 int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
-                accepted += orc_metro_site(theta, L, beta, seed, t, lat, k, substep, i);
+                accepted += orc_metro_site(theta, L, beta, seed, t, lat, k, substep, window, i);
             }
     return accepted;
 }
@@ -213,7 +215,7 @@ void orc_or_half(double *theta, int L, int colour)
  * n_acc (may be NULL) receives the accepted Metropolis moves per position.
  * ------------------------------------------------------------------------ */
 void orc_sweep(double *theta, int L, int R, const double *beta, uint64_t seed, uint32_t t,
-               int lat, int n_metro, int n_or, int64_t *n_acc)
+               int lat, int n_metro, int n_or, double window, int64_t *n_acc)
 {
     int64_t N = (int64_t)L * L * L;
     for (int k = 0; k < R; ++k) {
@@ -221,7 +223,7 @@ void orc_sweep(double *theta, int L, int R, const double *beta, uint64_t seed, u
         int64_t acc = 0;
         for (int s = 0; s < n_metro; ++s)
             for (int c = 0; c < 2; ++c)
-                acc += orc_metro_half(th, L, beta[k], seed, t, lat, k, s, c);
+                acc += orc_metro_half(th, L, beta[k], seed, t, lat, k, s, window, c);
         for (int s = 0; s < n_or; ++s)
             for (int c = 0; c < 2; ++c)
                 orc_or_half(th, L, c);
@@ -354,7 +356,7 @@ int orc_exchange(double *theta, double *E, int L, int R, const double *beta, uin
  * ------------------------------------------------------------------------ */
 void orc_run(double *theta, int L, int R, const double *beta, uint64_t seed, int lat,
              int ordered_start, uint32_t t0, uint32_t tau0, int n_sweeps, int n_metro,
-             int n_or, int exchange_every, double *obs, int64_t *n_metro_acc,
+             int n_or, double window, int exchange_every, double *obs, int64_t *n_metro_acc,
              int64_t *n_swap_acc)
 {
     int64_t N = (int64_t)L * L * L;
@@ -367,7 +369,7 @@ void orc_run(double *theta, int L, int R, const double *beta, uint64_t seed, int
     uint32_t tau = tau0;
     for (int s = 0; s < n_sweeps; ++s) {
         uint32_t t = t0 + (uint32_t)s;
-        orc_sweep(theta, L, R, beta, seed, t, lat, n_metro, n_or, acc);
+        orc_sweep(theta, L, R, beta, seed, t, lat, n_metro, n_or, window, acc);
         if (n_metro_acc)
             for (int k = 0; k < R; ++k) n_metro_acc[k] += acc[k];
         for (int k = 0; k < R; ++k) {

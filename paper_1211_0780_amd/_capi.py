@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "XY_OK", 1: "XY_ERR_ARG", 2: "XY_ERR_ODD_L", 3: "XY_ERR_OOM",
 EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange", "xy_run",
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
-           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused"]
+           "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused",
+           "xy_set_proposal_window"]
 
 
 class XYConfig(ctypes.Structure):
@@ -109,6 +110,8 @@ def lib():
         L.xy_set_tiling_fused.restype = i32
         L.xy_get_tiling_fused.argtypes = [vp, i32, ip, ip]
         L.xy_get_tiling_fused.restype = i32
+        L.xy_set_proposal_window.argtypes = [vp, ctypes.c_double]
+        L.xy_set_proposal_window.restype = i32
         L.xy_destroy.argtypes = [vp]
         L.xy_destroy.restype = None
         _lib = L

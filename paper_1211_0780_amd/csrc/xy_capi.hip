@@ -96,12 +96,12 @@ struct xy_ctx_s {
     uint64_t t = 0, tau = 0;
     bool e_fresh = false;          // d_E matches the current configurations
     bool bonds_fresh = false;      // d_bonds matches the current configurations
-    bool partials_are_sweep = false;
 
     std::vector<GraphEntry> graphs;
     std::vector<Tiling> tiles;  // FP32: per-lattice tile choice of the half-sweep kernels
     std::vector<Tiling> tiles2; // FP32: per-lattice tile choice of the fused over-relaxation
     bool fused_or = false;      // over-relaxation substeps as one fused kernel each
+    double window = 0.0;        // Metropolis proposal window (radians, 0: uniform)
     std::vector<LatDev> lat_or2;
     int items_or2 = 0, spt2 = 0;
     size_t lds2 = 0;
@@ -163,18 +163,18 @@ Tiling default_tiling(int L, int R)
     return t;
 }
 
-// Default tile of the fused over-relaxation kernel: at most two tile
-// columns per thread (its register footprint is about twice the half-sweep's).
+// Default tile of the fused over-relaxation kernel: up to three tile columns
+// per thread and z-chunks of at most 40 planes (measured best at L = 160).
 Tiling default_tiling2(int L)
 {
     const int half = L / 2;
     Tiling t;
     for (int d : divisors(L))
-        if (d * half <= 2 * kBlock) t.TY = d;
+        if (d * half <= 3 * kBlock && (size_t)(5 * d + 14) * half * 2 * sizeof(float) <= kMaxLds) t.TY = d;
     if (t.TY == 0) t.TY = 1;
     t.TZ = 1;
     for (int d : divisors(L))
-        if (d <= 24) t.TZ = d;
+        if (d <= 40) t.TZ = d;
     t.spt = spt_for(t.TY * half);
     return t;
 }
@@ -198,6 +198,8 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
     a.colour = colour;
     a.substep = substep;
     a.recheck = (c->flags & XY_F_NO_RECHECK) ? 0 : 1;
+    a.window = c->window;
+    a.window_t = (float)(c->window / 6.283185307179586476925286766559);
     a.partials = c->d_partials;
     a.macc = c->d_macc;
     a.rq = c->d_rq;
@@ -464,7 +466,7 @@ void build_layout(xy_ctx c)
             item2 += d.R * d.items_per_slot;
             c->lat_or2.push_back(d);
             c->spt2 = std::max(c->spt2, t.spt);
-            c->lds2 = std::max(c->lds2, (size_t)(2 * (t.TY + 4) + 2 * (t.TY + 2)) * d.half * 2 * sizeof(float));
+            c->lds2 = std::max(c->lds2, (size_t)(2 * (t.TY + 4) + 3 * (t.TY + 2)) * d.half * 2 * sizeof(float));
         }
         c->items_or2 = item2;
     }
@@ -915,7 +917,8 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
                 const int halo = (L > kBlock) ? 4 : 1;
                 double cost = 0.0;
                 for (int kind = 0; kind < 2 && !st; ++kind) {
-                    const int weight = kind == 0 ? n_metro : n_or;
+                    // over-relaxation substeps that run fused do not use this kernel
+                    const int weight = kind == 0 ? n_metro : n_or - fused_substeps(c, n_or);
                     if (weight == 0) continue;
                     const int kk = kind == 0 ? kMetro : kOver;
                     hipError_t e = launch_tile_f32(kk, false, t.spt, halo, items, lds, a, c->stream);  // warm
@@ -989,7 +992,7 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
                     a.partials = c->d_partials;
                     a.macc = c->d_macc;
                     a.rq = c->d_rq;
-                    const size_t lds = (size_t)(2 * (ty + 4) + 2 * (ty + 2)) * half * 2 * sizeof(float);
+                    const size_t lds = (size_t)(2 * (ty + 4) + 3 * (ty + 2)) * half * 2 * sizeof(float);
                     if (lds > kMaxLds) continue;
                     hipError_t e = launch_or2_f32(false, t.spt, items, lds, a, c->stream);
                     if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -1042,6 +1045,16 @@ xy_status xy_set_tiling(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz, int32
     return relayout(c);
 }
 
+xy_status xy_set_proposal_window(xy_ctx c, double window)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!(window >= 0.0) || window > 6.283185307179586476925286766559)
+        return fail(c, XY_ERR_ARG, "window must be in [0, 2 pi]");
+    c->window = window;
+    free_graphs(c);  // captured launches carry the old value
+    return XY_OK;
+}
+
 xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
@@ -1051,7 +1064,7 @@ xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
     if (ty < 1 || tz < 1 || L % ty != 0 || L % tz != 0)
         return fail(c, XY_ERR_ARG, "ty and tz must divide L");
     if (ty * (L / 2) > 8 * kBlock) return fail(c, XY_ERR_ARG, "ty * L/2 must be <= 2048");
-    if ((size_t)(4 * ty + 12) * (L / 2) * 2 * sizeof(float) > kMaxLds)
+    if ((size_t)(5 * ty + 14) * (L / 2) * 2 * sizeof(float) > kMaxLds)
         return fail(c, XY_ERR_ARG, "tile needs more than 64 KiB of LDS");
     Tiling t;
     t.TY = ty;

@@ -40,7 +40,7 @@ struct Ctl {
 // deferral changes nothing).
 struct RecheckEntry {
     int32_t li, slot, q;   // lattice, storage slot, index within the colour array
-    float cur, u0, u1;     // old angle, proposal, acceptance uniform (turns / unit)
+    float cur, prop, u1;   // old angle, proposal (turns), acceptance uniform
     int32_t fp32_accept;   // decision already applied by the half-sweep
     int32_t pad_;
 };
@@ -66,6 +66,8 @@ struct SweepArgs {
     int32_t colour;
     int32_t substep;
     int32_t recheck;           // FP32 Metropolis: re-decide in float64 near the threshold
+    float window_t;            // Metropolis proposal window in turns (0: uniform proposal)
+    double window;             // the same in radians, for the float64 kernels
     RecheckQueue *rq;          // where those decisions are queued
     double *partials;          // [items][kPartials] when measuring
     unsigned long long *macc;  // [R_total] accepted Metropolis moves by position

@@ -340,8 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const uint32_t i = ibase[s] + p + LL * (uint32_t)z;
                     const u32x4 r = philox4x32_10(i, t_sweep, c2, c3, a.k0, a.k1);
                     const float u0 = unit24f(r.x), u1 = unit24f(r.y);
+                    // uniform proposal (exact in turns) or theta + w (u0 - 1/2)
+                    const float prop = a.window_t > 0.0f
+                                           ? frac_turn(__builtin_fmaf(a.window_t, u0 - 0.5f, cur[s]))
+                                           : u0;
                     const f2 so = sincos_turns(cur[s]);
-                    const f2 sn = sincos_turns(u0);
+                    const f2 sn = sincos_turns(prop);
                     const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
                     const float pa = __expf(-beta * dE);
                     const bool acc = u1 < pa;
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                             e.slot = slot;
                             e.q = (int32_t)((sz + voff[s]) >> 2);
                             e.cur = cur[s];
-                            e.u0 = u0;
+                            e.prop = prop;
                             e.u1 = u1;
                             e.fp32_accept = acc ? 1 : 0;
                             e.pad_ = 0;
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                             atomicAdd(&a.rq->overflow, 1u);
                         }
                     }
-                    nv = acc ? u0 : cur[s];
+                    nv = acc ? prop : cur[s];
                     nacc += (acc && ok[s]) ? 1ull : 0ull;
                 }
                 if constexpr (MEAS || KIND == kMeas) {
@@ -459,17 +463,24 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
         const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(src, 0);
         const int rows1 = TY + 4, rows0 = TY + 2;
         f2 *P1[2] = {lds, lds + rows1 * half};
-        f2 *P0[2] = {lds + 2 * rows1 * half, lds + 2 * rows1 * half + rows0 * half};
+        f2 *P0base = lds + 2 * rows1 * half;
+        auto P0 = [&](int b) { return P0base + b * rows0 * half; };
         auto wrapy = [L](int y) { return y < 0 ? y + L : (y >= L ? y - L : y); };
         auto wrapz = wrapy;
         auto xm = [half](int j) { return j == 0 ? half - 1 : j - 1; };
         auto xp = [half](int j) { return j + 1 == half ? 0 : j + 1; };
 
         // ---- slot geometry (constant over z) ----
+        // A tile column's LDS index is its in-plane index plus a uniform
+        // shift (P1 rows start two rows above the tile, P0 rows one), and its
+        // x-neighbour is a fixed delta away on even and on odd steps: for
+        // colour 0 at (y, z) and colour 1 at (y, z-1) alike it is j+1 when
+        // (y + z) is odd, j-1 when even (wrapping within the row).
         uint32_t voffT[SPT];
-        int l1T[SPT], l0T[SPT], l1xe[SPT], l1xo[SPT], l0xe[SPT], l0xo[SPT];
+        int dxe[SPT], dxo[SPT];
         bool okT[SPT], pz0[SPT];
         const int zs = wrapz(z0 - 1);  // first step's plane
+        const int sh1 = 2 * half - y0 * half, sh0 = half - y0 * half;
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
             const int f = tid + s * kBlock;
@@ -477,18 +488,14 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             const int fl = okT[s] ? f : 0;
             const int yl = fl / half, j = fl - yl * half, y = y0 + yl;
             voffT[s] = (uint32_t)(y * half + j) * 4u;
-            l1T[s] = (yl + 2) * half + j;
-            l0T[s] = (yl + 1) * half + j;
-            // x-neighbour on the first step (plane zs) and on the next: for
-            // colour 0 at (y, z) and colour 1 at (y, z-1) alike it is j+1
-            // when (y + z) is odd, j-1 when even
             const bool podd = ((y + zs) & 1) != 0;
             pz0[s] = podd;
-            l1xe[s] = (yl + 2) * half + (podd ? xp(j) : xm(j));
-            l1xo[s] = (yl + 2) * half + (podd ? xm(j) : xp(j));
-            l0xe[s] = (yl + 1) * half + (podd ? xp(j) : xm(j));
-            l0xo[s] = (yl + 1) * half + (podd ? xm(j) : xp(j));
+            const int dp = xp(j) - j, dm = xm(j) - j;
+            dxe[s] = podd ? dp : dm;
+            dxo[s] = podd ? dm : dp;
         }
+        auto l1T = [&](int s) { return (int)(voffT[s] >> 2) + sh1; };
+        auto l0T = [&](int s) { return (int)(voffT[s] >> 2) + sh0; };
         const bool okH = tid < 2 * half;
         const int eH = okH ? tid : 0;
         const int rH = eH >= half, jH = eH - rH * half;
@@ -505,10 +512,14 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
 
         // ---- prologue: state for the first step (plane zs = z0-1) ----
         auto pb = [&](int z) { return (uint32_t)wrapz(z) * plane_b; };
-        f2 c1m[SPT], c1c[SPT], c1p[SPT], c0n1[SPT], c0n2[SPT];
+        // Old colour 1 of plane z-1 stays in the P1 buffer that is rewritten
+        // only at the end of step z, and new colour 0 of planes z-1, z-2 in
+        // the other two of three P0 buffers, so only plane z+1 (old colour 1)
+        // and plane z (new colour 0) are held in registers.
+        f2 c1p[SPT];
         float r1m[SPT], r1c[SPT], r1p[SPT], t0[SPT];
         float aT1[SPT], aT0[SPT], bT1[SPT], bT0[SPT];
-        f2 hm, hc, hp;
+        f2 hp;
         float ht0, aH1, aH0, bH1, bH0, aO, bO;
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
@@ -518,15 +529,12 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             t0[s] = bload(r0s, voffT[s], pb(z0 - 1));
             aT1[s] = bload(r1s, voffT[s], pb(z0 + 1));
             aT0[s] = bload(r0s, voffT[s], pb(z0));
-            c1m[s] = sincos_turns(r1m[s]);
-            c1c[s] = sincos_turns(r1c[s]);
+            P1[1][l1T(s)] = sincos_turns(r1m[s]);
+            P1[0][l1T(s)] = sincos_turns(r1c[s]);
             c1p[s] = sincos_turns(r1p[s]);
-            c0n1[s] = f2{0.f, 0.f};
-            c0n2[s] = f2{0.f, 0.f};
-            P1[0][l1T[s]] = c1c[s];
         }
-        hm = sincos_turns(bload(r1s, voffH, pb(z0 - 2)));
-        hc = sincos_turns(bload(r1s, voffH, pb(z0 - 1)));
+        const f2 hm0 = sincos_turns(bload(r1s, voffH, pb(z0 - 2)));
+        const f2 hc0 = sincos_turns(bload(r1s, voffH, pb(z0 - 1)));
         hp = sincos_turns(bload(r1s, voffH, pb(z0)));
         ht0 = bload(r0s, voffH, pb(z0 - 1));
         aH1 = bload(r1s, voffH, pb(z0 + 1));
@@ -534,7 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
         const f2 o0 = sincos_turns(bload(r1s, voffO, pb(z0 - 1)));
         aO = bload(r1s, voffO, pb(z0));
         if (okH) {
-            P1[0][l1H] = hc;
+            P1[1][l1H] = hm0;
+            P1[0][l1H] = hc0;
             P1[0][l1O] = o0;
         }
         lds_barrier();
@@ -549,9 +558,11 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
                         float (&nxtT0)[SPT], float &nxtH1, float &nxtH0, float &nxtO) {
             const int z = z0 - 1 + zz;
             const f2 *p1 = P1[par];
-            f2 *p0w = P0[par];
-            const f2 *p0r = P0[par ^ 1];
-            f2 *p1n = P1[par ^ 1];
+            f2 *p1n = P1[par ^ 1];           // plane z-1 until rewritten with z+1 at the end
+            const int m3 = zz % 3;
+            f2 *p0w = P0(m3);                  // new colour 0, plane z
+            const f2 *p0r = P0(m3 == 0 ? 2 : m3 - 1);   // plane z-1
+            const f2 *p0r2 = P0(m3 == 2 ? 0 : m3 + 1);  // plane z-2
             {
                 // last planes needed: old colour 1 at z0+TZ+1 (z neighbour of
                 // a at z0+TZ), old colour 0 and the outer rows at z0+TZ; all
@@ -575,18 +586,20 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             f2 c0cur[SPT];
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
-                const int lx = par ? l1xo[s] : l1xe[s];
-                const f2 n1 = p1[l1T[s] - half], n2 = p1[l1T[s] + half], n3 = p1[l1T[s]], n4 = p1[lx];
-                const float hx = ((c1m[s].c + c1p[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
-                const float hy = ((c1m[s].s + c1p[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
+                const int lc = l1T(s), lx = lc + (par ? dxo[s] : dxe[s]);
+                const f2 n1 = p1[lc - half], n2 = p1[lc + half], n3 = p1[lc], n4 = p1[lx];
+                const f2 c1m = p1n[lc];
+                const float hx = ((c1m.c + c1p[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
+                const float hy = ((c1m.s + c1p[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
                 const float nv = overrelax_turns(t0[s], hx, hy);
                 if (store_a && okT[s]) bstore(nv, r0d, voffT[s], sz);
                 c0cur[s] = sincos_turns(nv);
-                p0w[l0T[s]] = c0cur[s];
+                p0w[l0T(s)] = c0cur[s];
             }
             {
                 const int lx = par ? l1Hxo : l1Hxe;
                 const f2 n1 = p1[l1H - half], n2 = p1[l1H + half], n3 = p1[l1H], n4 = p1[lx];
+                const f2 hm = p1n[l1H];
                 const float hx = ((hm.c + hp.c) + (n1.c + n2.c)) + (n3.c + n4.c);
                 const float hy = ((hm.s + hp.s) + (n1.s + n2.s)) + (n3.s + n4.s);
                 const f2 hv = sincos_turns(overrelax_turns(ht0, hx, hy));
@@ -596,11 +609,11 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             if (zz >= 2) {
 #pragma unroll
                 for (int s = 0; s < SPT; ++s) {
-                    const int lx = par ? l0xo[s] : l0xe[s];
-                    const f2 m1 = p0r[l0T[s] - half], m2 = p0r[l0T[s] + half], m3 = p0r[l0T[s]],
-                             m4 = p0r[lx];
-                    const float hx = ((c0n2[s].c + c0cur[s].c) + (m1.c + m2.c)) + (m3.c + m4.c);
-                    const float hy = ((c0n2[s].s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
+                    const int lc = l0T(s), lx = lc + (par ? dxo[s] : dxe[s]);
+                    const f2 m1 = p0r[lc - half], m2 = p0r[lc + half], m3 = p0r[lc], m4 = p0r[lx];
+                    const f2 c0m2 = p0r2[lc];
+                    const float hx = ((c0m2.c + c0cur[s].c) + (m1.c + m2.c)) + (m3.c + m4.c);
+                    const float hy = ((c0m2.s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
                     const float nv = overrelax_turns(r1m[s], hx, hy);
                     if (okT[s]) bstore(nv, r1d, voffT[s], szm);
                     if constexpr (MEAS) {
@@ -611,21 +624,20 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
                             const bool podd = pz0[s] != (par != 0);
                             const f2 xpv = podd ? m4 : m3, xmv = podd ? m3 : m4;
                             const f2 sc = sincos_turns(nv);
-                            const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0n2[s].c};
-                            const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0n2[s].s};
-                            measure_site(acc, sc.c, sc.s, c0n1[s].c, c0n1[s].s, nc, ns);
+                            const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0m2.c};
+                            const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0m2.s};
+                            // m3 is the colour-0 site with the same storage index
+                            measure_site(acc, sc.c, sc.s, m3.c, m3.s, nc, ns);
                         }
                     }
                 }
             }
-            // next plane of old colour 1 into LDS; shift the z windows
+            // next plane of old colour 1 into LDS (over plane z-1, which
+            // every lane must have finished reading) and shift the z windows
+            lds_barrier();
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
-                p1n[l1T[s]] = c1p[s];
-                c0n2[s] = c0n1[s];
-                c0n1[s] = c0cur[s];
-                c1m[s] = c1c[s];
-                c1c[s] = c1p[s];
+                p1n[l1T(s)] = c1p[s];
                 c1p[s] = sincos_turns(preT1[s]);
                 r1m[s] = r1c[s];
                 r1c[s] = r1p[s];
@@ -637,8 +649,6 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
                 p1n[l1H] = hp;
                 p1n[l1O] = onext;
             }
-            hm = hc;
-            hc = hp;
             hp = sincos_turns(preH1);
             ht0 = preH0;
             lds_barrier();
@@ -696,12 +706,12 @@ __global__ __launch_bounds__(kBlock) void k_recheck(const LatDev *lats, float *a
         }
         double so, co, sp, cp;
         sincos((double)en.cur * twopi, &so, &co);
-        sincos((double)en.u0 * twopi, &sp, &cp);
+        sincos((double)en.prop * twopi, &sp, &cp);
         const double dE = (co - cp) * hx + (so - sp) * hy;
         const int k = pos[d.pos_base + en.slot];
         const bool acc = (double)en.u1 < exp(-beta[d.pos_base + k] * dE);
         if ((int)acc != en.fp32_accept) {
-            own[en.q] = acc ? en.u0 : en.cur;
+            own[en.q] = acc ? en.prop : en.cur;
             atomicAdd(macc + d.pos_base + k, acc ? 1ull : ~0ull);  // +1 or -1
         }
     }
@@ -780,7 +790,12 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
                                (uint32_t)L * ((uint32_t)y + (uint32_t)L * (uint32_t)z);
             const u32x4 r = philox4x32_10(i, a.ctl->t, ((uint32_t)d.lat << 16) | (uint32_t)k,
                                           (kPhaseMetro << 24) | (uint32_t)a.substep, a.k0, a.k1);
-            const double prop = twopi * unit24d(r.x);
+            double prop = twopi * unit24d(r.x);
+            if (a.window > 0.0) {
+                prop = fmod(th + a.window * (unit24d(r.x) - 0.5), twopi);
+                if (prop < 0.0) prop += twopi;
+                if (prop >= twopi) prop = 0.0;
+            }
             const double u = unit24d(r.y);
             double so, co, sp, cp;
             sincos(th, &so, &co);

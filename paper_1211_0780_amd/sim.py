@@ -129,6 +129,10 @@ class Sim:
     def set_tiling(self, lattice, ty, tz, grid_cap=0):
         C.check(C.lib().xy_set_tiling(self._ctx, int(lattice), int(ty), int(tz), int(grid_cap)), self._ctx)
 
+    def set_proposal_window(self, window):
+        """0: uniform Metropolis proposal; 0 < window <= 2 pi: theta + window (U - 1/2)."""
+        C.check(C.lib().xy_set_proposal_window(self._ctx, float(window)), self._ctx)
+
     def set_tiling_fused(self, lattice, ty, tz):
         C.check(C.lib().xy_set_tiling_fused(self._ctx, int(lattice), int(ty), int(tz)), self._ctx)
 

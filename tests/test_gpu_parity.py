@@ -296,3 +296,58 @@ def test_bond_sums_ring_matches_eager(gpu):
         eb = b.bond_sums()
         assert np.allclose(bonds[sidx].cpu().numpy(), eb, rtol=1e-12, atol=1e-8)
         b.exchange()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_windowed_metropolis_half_sweep(gpu, prec):
+    """Restricted-window proposal theta' = theta + w (U - 1/2): every site of
+    both colours against the oracle's half-sweep from the same state; a
+    decision may differ only within 1e-6 of the threshold."""
+    L, seed, w = 12, 44, 1.1
+    betas = [0.45, 2.0]
+    s = make(L, betas, seed, prec)
+    s.set_proposal_window(w)
+    s.sweep(1, 2)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    t = s.counters()[0]
+    before = gpu_states(s)
+    s.sweep(1, 0)
+    after = gpu_states(s)
+    key = P.key_of(seed)
+    for k, beta in enumerate(betas):
+        mid = before[k].copy()
+        for c in (0, 1):
+            ref = mid.copy()
+            oracle.metro_half(ref, L, beta, seed, t, 0, k, 0, c, window=w)
+            m = colour_mask(L, c)
+            d = circ(after[k], ref)[m]
+            bad = np.flatnonzero(d > tol)
+            hx, hy = field_numpy(mid, L)
+            for i in np.flatnonzero(m)[bad]:
+                r = P.philox4x32_10(P.counter(int(i), t, 0, k, P.PHASE_METRO, 0), key)
+                prop = (mid[i] + w * (P.uniform(r[0]) - 0.5)) % (2 * np.pi)
+                dE = (np.cos(mid[i]) - np.cos(prop)) * hx[i] + (np.sin(mid[i]) - np.sin(prop)) * hy[i]
+                assert abs(P.uniform(r[1]) - np.exp(-beta * dE)) < 1e-6
+            if prec == "fp64":
+                assert bad.size == 0
+            mid[m] = after[k][m]
+    acc = s.metro_accepts()
+    assert acc[1] > 0
+
+
+def test_windowed_proposal_long_run_matches_oracle(gpu):
+    """L = 8 at beta = 1.0 with window 1.0: same equilibrium law as the oracle's chain."""
+    import torch
+    from stats_util import binned_mean
+    L, beta, seed, n, w = 8, 1.0, 6, 8000, 1.0
+    s = make(L, [beta], seed, "fp32")
+    s.set_proposal_window(w)
+    obs = torch.zeros((n, 1, 5), dtype=torch.float64, device=gpu)
+    s.run(n, 1, 1, exchange_every=0, obs=obs)
+    og = obs.cpu().numpy()[:, 0]
+    _, oo, _, _ = oracle.run(L, [beta], seed, n, 1, 1, exchange_every=0, window=w)
+    oo = oo[:, 0]
+    for c in (1, 3):
+        a, ea = binned_mean(og[:, c])
+        b, eb = binned_mean(oo[:, c])
+        assert abs(a - b) <= 3 * np.hypot(ea, eb), (c, a, b, ea, eb)

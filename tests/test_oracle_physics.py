@@ -128,3 +128,20 @@ def test_binder_crossing_brackets_beta_c(orc):
     hi_small, hi_big = res[(0.49, 6)], res[(0.49, 12)]
     assert lo_small[0] - lo_big[0] > 3 * np.hypot(lo_small[1], lo_big[1])
     assert hi_big[0] - hi_small[0] > 3 * np.hypot(hi_small[1], hi_big[1])
+
+
+@pytest.mark.parametrize("window", [0.7, 2.5])
+def test_windowed_proposal_keeps_the_von_mises_law(orc, window):
+    """The restricted-window proposal theta' = theta + w (U - 1/2) is symmetric,
+    so the single-site law in a frozen field stays von Mises exp(6 beta cos)."""
+    L, beta = 6, 1.0
+    th = orc.init(L, 1, 31)[0].copy()
+    th[~colour_mask(L, 0)] = 0.0
+    m0 = colour_mask(L, 0)
+    c1 = []
+    for t in range(3000):
+        orc.metro_half(th, L, beta, 31, t, 0, 0, 0, 0, window=window)
+        c1.append(np.cos(th[m0]).mean())
+    k = 6 * beta
+    mu, err = binned_mean(c1, discard=0.1)
+    assert abs(mu - i1(k) / i0(k)) < 4 * err + 1e-4

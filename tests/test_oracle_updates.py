@@ -223,3 +223,29 @@ def test_exchange_acceptance_rate(orc):
         acc += orc.exchange(None, E, L, beta, 17, tau, 0, None)
     p = np.exp(delta)
     assert abs(acc / n - p) < 4 * np.sqrt(p * (1 - p) / n)
+
+
+def test_windowed_metropolis_proposal_and_decisions(orc):
+    """Window w: proposal wrap(theta + w (U(r0) - 1/2)), decided by u < exp(-beta dE)."""
+    L, seed, t, lat, k, s, beta, w = 6, 12, 4, 0, 1, 0, 0.6, 1.3
+    th0 = orc.init(L, 1, seed)[0].copy()
+    th = th0.copy()
+    orc.metro_half(th, L, beta, seed, t, lat, k, s, 0, window=w)
+    hx, hy = field(th0, L)
+    hx, hy = hx.ravel(), hy.ravel()
+    key = P.key_of(seed)
+    moved = 0
+    for i in np.flatnonzero(colour_mask(L, 0).ravel()):
+        r = P.philox4x32_10(P.counter(int(i), t, lat, k, P.PHASE_METRO, s), key)
+        prop = (th0[i] + w * (P.uniform(r[0]) - 0.5)) % (2 * np.pi)
+        u = P.uniform(r[1])
+        dE = (np.cos(th0[i]) - np.cos(prop)) * hx[i] + (np.sin(th0[i]) - np.sin(prop)) * hy[i]
+        p = np.exp(-beta * dE)
+        if abs(u - p) < 1e-12:
+            continue
+        if u < p:
+            assert circ(th[i], prop) < 1e-13
+            moved += 1
+        else:
+            assert th[i] == th0[i]
+    assert moved > 0
