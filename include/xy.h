@@ -169,12 +169,13 @@ xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
                  int32_t exchange_every, double *obs_dev);
 
 /*
- * xy_sweep with every kernel launch bracketed by HIP events on the
- * context's stream (profiling aid; same result as xy_sweep).  ms[0..3]
- * receive the summed device time of the Metropolis half-sweeps, the
- * over-relaxation half-sweeps, the fused over-relaxation substeps (one
- * launch updates both colours) and everything else the sweep launched;
- * launches[0..3] the matching kernel counts.  Waits.
+ * xy_sweep with each group of consecutive launches of one kind bracketed by
+ * HIP events on the context's stream (profiling aid; same result as
+ * xy_sweep).  ms[0..3] receive the device time of the Metropolis half-sweeps
+ * (with their float64 re-decision kernels), the over-relaxation
+ * half-sweeps, the fused over-relaxation substeps (one launch updates both
+ * colours) and the counter update; launches[0..3] the number of half-sweep,
+ * half-sweep, fused and counter launches in each group.  Waits.
  */
 xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *ms,
                             int32_t *launches);

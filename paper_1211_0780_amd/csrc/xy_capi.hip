@@ -653,62 +653,48 @@ xy_status xy_sweep_profiled(xy_ctx c, int32_t n_metro, int32_t n_or, double *ms,
         return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
     if (c->t >= 0xffffffffull) return fail(c, XY_ERR_STATE, "sweep counter would overflow 32 bits");
     const int n_fused = fused_substeps(c, n_or);
-    struct Rec {
-        int kind;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    auto cleanup = [&]() {
-        for (auto &r : recs) {
-            if (r.a) (void)hipEventDestroy(r.a);
-            if (r.b) (void)hipEventDestroy(r.b);
-        }
-    };
-    auto timed = [&](int kind, auto &&launch) -> xy_status {
-        Rec r{kind, nullptr, nullptr};
-        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
-            recs.push_back(r);
+    // One event pair per group of consecutive launches of one kind (events
+    // between every launch would add their own overhead to each kernel):
+    // Metropolis half-sweeps with their re-decision kernels, fused
+    // substeps, over-relaxation half-sweeps, and the counter update.
+    hipEvent_t ev[8] = {};
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &x : ev)
+                if (x) (void)hipEventDestroy(x);
             return fail(c, XY_ERR_HIP, "hipEventCreate failed");
         }
-        recs.push_back(r);
-        (void)hipEventRecord(r.a, c->stream);
-        xy_status st = launch();
-        (void)hipEventRecord(r.b, c->stream);
-        return st;
-    };
+    const int counts[4] = {2 * n_metro, 2 * (n_or - n_fused), n_fused, 1};
     xy_status st = XY_OK;
+    (void)hipEventRecord(ev[0], c->stream);
     for (int s = 0; s < n_metro && !st; ++s)
-        for (int col = 0; col < 2 && !st; ++col)
-            st = timed(0, [&] { return launch_half(c, kMetro, col, s, false); });
-    for (int s = 0; s < n_fused && !st; ++s) {
-        void *from = (s & 1) ? c->ang2 : c->ang;
-        void *to = (s & 1) ? c->ang : c->ang2;
-        st = timed(2, [&] { return launch_or2(c, from, to, false); });
-    }
+        for (int col = 0; col < 2 && !st; ++col) st = launch_half(c, kMetro, col, s, false);
+    (void)hipEventRecord(ev[1], c->stream);
+    (void)hipEventRecord(ev[4], c->stream);
+    for (int s = 0; s < n_fused && !st; ++s)
+        st = launch_or2(c, (s & 1) ? c->ang2 : c->ang, (s & 1) ? c->ang : c->ang2, false);
+    (void)hipEventRecord(ev[5], c->stream);
+    (void)hipEventRecord(ev[2], c->stream);
     for (int s = n_fused; s < n_or && !st; ++s)
-        for (int col = 0; col < 2 && !st; ++col)
-            st = timed(1, [&] { return launch_half(c, kOver, col, s, false); });
-    if (!st)
-        st = timed(3, [&]() -> xy_status {
-            hipError_t e = launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream);
-            return e == hipSuccess ? XY_OK : fail(c, XY_ERR_HIP, "tick launch failed");
-        });
+        for (int col = 0; col < 2 && !st; ++col) st = launch_half(c, kOver, col, s, false);
+    (void)hipEventRecord(ev[3], c->stream);
+    (void)hipEventRecord(ev[6], c->stream);
+    if (!st && launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream) != hipSuccess)
+        st = fail(c, XY_ERR_HIP, "tick launch failed");
+    (void)hipEventRecord(ev[7], c->stream);
     if (!st && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, XY_ERR_HIP, "sync failed");
     if (!st) {
+        const int pairs[4][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}};
         for (int k = 0; k < 4; ++k) {
-            ms[k] = 0.0;
-            launches[k] = 0;
-        }
-        for (auto &r : recs) {
             float t = 0.f;
-            (void)hipEventElapsedTime(&t, r.a, r.b);
-            ms[r.kind] += t;
-            launches[r.kind] += 1;
+            (void)hipEventElapsedTime(&t, ev[pairs[k][0]], ev[pairs[k][1]]);
+            ms[k] = counts[k] ? (double)t : 0.0;
+            launches[k] = counts[k];
         }
         c->t += 1;
         c->e_fresh = c->bonds_fresh = false;
     }
-    cleanup();
+    for (auto &e : ev) (void)hipEventDestroy(e);
     return st;
 }
 

@@ -56,29 +56,31 @@ __device__ __forceinline__ void block_store_partials(const double (&v)[kPartials
 
 // Measurement terms of one colour-1 site i with unit vector (c, s), its six
 // colour-0 neighbours split by direction (+x, -x, +y, -y, +z, -z) and the
-// colour-0 partner site at the same storage index (cz, sz):
+// colour-0 partner site at the same storage index (pc, ps):
 //   E  -= S_i . h_i                        (every bond has one colour-1 end)
 //   M  += S_i + S_partner                  (each site counted once)
 //   C_mu += S_i . (S_{i+mu} + S_{i-mu})     bonds (i, i+mu) and (i-mu, i)
 //   I_mu += sin(th_i - th_{i+mu}) - sin(th_i - th_{i-mu})
+// Each site's terms are formed in the precision of its inputs (float32 on
+// the float32 path: a few 1e-7 relative, like the inputs themselves) and
+// accumulated in float64.
 template <typename T>
 __device__ __forceinline__ void measure_site(double (&acc)[kPartials], T c, T s, T pc, T ps,
                                              const T (&nc)[6], const T (&ns)[6])
 {
-    const double cd = (double)c, sd = (double)s;
-    double Esum = 0.0;
+    T Esum = T(0);
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
-        const double cp = (double)nc[2 * mu], sp = (double)ns[2 * mu];
-        const double cm = (double)nc[2 * mu + 1], sm = (double)ns[2 * mu + 1];
-        const double Cm = cd * (cp + cm) + sd * (sp + sm);
-        acc[3 + mu] += Cm;
-        acc[6 + mu] += sd * (cp - cm) - cd * (sp - sm);
+        const T cp = nc[2 * mu], sp = ns[2 * mu];
+        const T cm = nc[2 * mu + 1], sm = ns[2 * mu + 1];
+        const T Cm = c * (cp + cm) + s * (sp + sm);
+        acc[3 + mu] += (double)Cm;
+        acc[6 + mu] += (double)(s * (cp - cm) - c * (sp - sm));
         Esum += Cm;
     }
-    acc[0] -= Esum;
-    acc[1] += cd + (double)pc;
-    acc[2] += sd + (double)ps;
+    acc[0] -= (double)Esum;
+    acc[1] += (double)c + (double)pc;
+    acc[2] += (double)s + (double)ps;
 }
 
 __device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned long long *dst)
