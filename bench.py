@@ -12,8 +12,8 @@ Prints one JSON line:
             updates both colours), against 8 TB/s HBM at 12 algorithmic bytes
             per site-update (the unfused half-sweep's reads and writes; the
             fused pass moves less, so this fraction can exceed what an unfused
-            kernel could reach), timed with HIP events around each launch on
-            the simulation's stream
+            kernel could reach), timed with HIP events on the simulation's
+            stream around each group of consecutive launches of one kind
   cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload
   fp64_plain    the plain FP64 single-replica kernels at L = 160, for reference
 """
@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=3,
+    ap.add_argument("--profile-steps", type=int, default=5,
                     help="extra eagerly launched sweeps timed per kernel with HIP events")
     ap.add_argument("--tiling", default=DEFAULT_TILING,
                     help="'TYxTZ' for the tiled half-sweep, or 'auto' to run the autotuner "
@@ -234,6 +234,18 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+
+    # per-kernel device time: HIP events on the sweep's stream around each group
+    # of consecutive launches of one kind (group time / launches in the group).
+    # These sweeps follow the timed region at once: after even a fraction of a
+    # second of idling the GPU clocks down and the first launches run slower.
+    tot, cnt = {}, {}
+    for _ in range(args.profile_steps):
+        ms, n = sim.sweep_profiled(N_METRO, N_OR)
+        for k in ms:
+            tot[k] = tot.get(k, 0.0) + ms[k]
+            cnt[k] = cnt.get(k, 0) + n[k]
+    print(f"[bench] per-kernel timing over {args.profile_steps} sweeps done", file=sys.stderr, flush=True)
     ms_total = ev0.elapsed_time(ev1)
     sec = ms_total / 1e3
     updates = args.steps * (N_METRO + N_OR) * N * R
@@ -241,15 +253,6 @@ def main():
     o = obs[: args.steps].cpu().numpy()
     if not np.all(np.isfinite(o)):
         raise SystemExit("non-finite observables")
-
-    # per-kernel device time, HIP events around each launch on the same stream
-    print(f"[bench] per-kernel timing over {args.profile_steps} sweeps", file=sys.stderr, flush=True)
-    tot, cnt = {}, {}
-    for _ in range(args.profile_steps):
-        ms, n = sim.sweep_profiled(N_METRO, N_OR)
-        for k in ms:
-            tot[k] = tot.get(k, 0.0) + ms[k]
-            cnt[k] = cnt.get(k, 0) + n[k]
     avg = {k: (tot[k] / cnt[k] if cnt[k] else None) for k in tot}
     khash = kernel_source_hash()
     if cnt["over_fused"]:

@@ -7,8 +7,9 @@
 namespace xy {
 
 constexpr int kBlock = 256;  // threads per workgroup of the tiled and plain kernels
-// measurement partials per work item: E, Mx, My, C_x, C_y, C_z, I_x, I_y, I_z
-constexpr int kPartials = 9;
+// measurement partials per work item: Mx, My, C_x, C_y, C_z, I_x, I_y, I_z
+// (the energy is E = -(C_x + C_y + C_z), formed after the reduction)
+constexpr int kPartials = 8;
 
 // One lattice of a batch, as the kernels see it.  All offsets are in angle
 // elements (float for FP32, double for FP64).

@@ -57,30 +57,33 @@ __device__ __forceinline__ void block_store_partials(const double (&v)[kPartials
 // Measurement terms of one colour-1 site i with unit vector (c, s), its six
 // colour-0 neighbours split by direction (+x, -x, +y, -y, +z, -z) and the
 // colour-0 partner site at the same storage index (pc, ps):
-//   E  -= S_i . h_i                        (every bond has one colour-1 end)
-//   M  += S_i + S_partner                  (each site counted once)
+//   M    += S_i + S_partner                (each site counted once)
 //   C_mu += S_i . (S_{i+mu} + S_{i-mu})     bonds (i, i+mu) and (i-mu, i)
 //   I_mu += sin(th_i - th_{i+mu}) - sin(th_i - th_{i-mu})
-// Each site's terms are formed in the precision of its inputs (float32 on
-// the float32 path: a few 1e-7 relative, like the inputs themselves) and
-// accumulated in float64.
+// Every bond has exactly one colour-1 end, so the C_mu count each bond once
+// and the energy of Eq. (1) is E = -(C_x + C_y + C_z).  Each site's terms
+// are formed in the precision of its inputs (float32 on the float32 path: a
+// few 1e-7 relative, like the inputs themselves) and accumulated in float64.
+// The fused multiply-adds are written out so that every kernel that inlines
+// this forms bit-identical terms (left to the compiler, contraction of the
+// products may differ between instantiations).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ void measure_site(double (&acc)[kPartials], T c, T s, T pc, T ps,
                                              const T (&nc)[6], const T (&ns)[6])
 {
-    T Esum = T(0);
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
         const T cp = nc[2 * mu], sp = ns[2 * mu];
         const T cm = nc[2 * mu + 1], sm = ns[2 * mu + 1];
-        const T Cm = c * (cp + cm) + s * (sp + sm);
-        acc[3 + mu] += (double)Cm;
-        acc[6 + mu] += (double)(s * (cp - cm) - c * (sp - sm));
-        Esum += Cm;
+        const T ssum = s * (sp + sm), cdif = c * (sp - sm);
+        acc[2 + mu] += (double)fma_t(c, cp + cm, ssum);
+        acc[5 + mu] += (double)fma_t(s, cp - cm, -cdif);
     }
-    acc[0] -= (double)Esum;
-    acc[1] += (double)c + (double)pc;
-    acc[2] += (double)s + (double)ps;
+    acc[0] += (double)c + (double)pc;
+    acc[1] += (double)s + (double)ps;
 }
 
 __device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned long long *dst)
@@ -893,7 +896,7 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
 #pragma unroll
             for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
             if (lane == 0) {
-                const double E = v[0], mx = v[1], my = v[2];
+                const double E = -(v[2] + v[3] + v[4]), mx = v[0], my = v[1];
                 E_slot[pb + r] = E;
                 if (!isfinite(E) || !isfinite(mx) || !isfinite(my)) atomicOr(bad, 1);
                 const int kk = pos[pb + r];
@@ -910,7 +913,7 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
                 if (bout) {
                     double *o = bout + 6 * (int64_t)(pb + kk);
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) o[q] = v[3 + q];
+                    for (int q = 0; q < 6; ++q) o[q] = v[2 + q];
                 }
             }
         }

@@ -111,9 +111,10 @@ class Sim:
         return out
 
     def sweep_profiled(self, n_metro=1, n_or=1):
-        """xy_sweep with per-kernel HIP-event timing: returns summed milliseconds
-        and launch counts keyed 'metro', 'over' (half-sweeps), 'over_fused'
-        (fused substeps) and 'other'."""
+        """xy_sweep with HIP events around each group of consecutive launches of
+        one kind: returns the group's milliseconds and its launch count, keyed
+        'metro' (half-sweeps with their re-decision kernels), 'over'
+        (half-sweeps), 'over_fused' (fused substeps) and 'other'."""
         ms = (ctypes.c_double * 4)()
         n = (ctypes.c_int32 * 4)()
         C.check(C.lib().xy_sweep_profiled(self._ctx, int(n_metro), int(n_or), ms, n), self._ctx)

@@ -193,3 +193,22 @@ def test_fused_measurement_equals_half_sweep_measurement(gpu):
     assert a.permutation() == b.permutation()
     assert np.allclose(oa.cpu().numpy(), ob.cpu().numpy(), rtol=1e-12, atol=1e-9)
     assert np.allclose(ba.cpu().numpy(), bb.cpu().numpy(), rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_profiled_sweep_equals_sweep(gpu, fused):
+    """The profiling variant launches the same kernels in the same order as
+    xy_sweep and reports one launch count per kernel group."""
+    from paper_1211_0780_amd.sim import Sim
+    betas = [0.44, 0.45, 0.46]
+    a = Sim(12, [betas], seed=23, prec="fp32", fused_or=fused)
+    b = Sim(12, [betas], seed=23, prec="fp32", fused_or=fused)
+    for _ in range(2):
+        ms, n = a.sweep_profiled(1, 5)
+        b.sweep(1, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.counters() == b.counters()
+    nf = 4 if fused else 0
+    assert n == {"metro": 2, "over": 2 * (5 - nf), "over_fused": nf, "other": 1}
+    assert all(ms[k] > 0 for k in n if n[k]) and all(ms[k] == 0 for k in n if not n[k])
