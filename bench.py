@@ -37,7 +37,7 @@ BYTES_PER_UPDATE_F64 = 24.0
 L, R, SEED = 160, 32, 4
 BETA_LO, BETA_HI = 0.4538, 0.4546
 N_METRO, N_OR = 1, 10
-DEFAULT_TILING = "8x20"
+DEFAULT_TILING = "16x20"
 DEFAULT_TILING_FUSED = "8x40"
 
 
@@ -157,6 +157,11 @@ def digest_traffic(fetch_csv, write_csv):
     out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
     out["kernel"] = kind
     out["algorithmic_bytes_per_launch"] = BYTES_PER_UPDATE_F32 * R * L ** 3 / (1 if kind == "fused" else 2)
+    probe = "python3 bench.py --traffic-probe" + ("" if kind == "fused" else " --unfused")
+    out["commands"] = [
+        f"rocprofv3 --pmc {c} -d <dir> -o run --output-format csv -- {probe}"
+        for c in ("FETCH_SIZE", "WRITE_SIZE")
+    ] + [f"python3 bench.py --digest-traffic <FETCH_SIZE csv> <WRITE_SIZE csv>"]
     path = traffic_path(kind)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)

@@ -329,8 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 for (int h = 0; h < HALO; ++h) nxt_h[h] = bload(ro, hvoff[h], s2);
             }
 
+            // Columns past the tile (ok false) are skipped: with TY * L/2 not a
+            // multiple of the block size whole wavefronts have nothing to do
+            // in the last column, and the branch lets them skip it.
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
+                if (!ok[s]) continue;
                 const f2 n1 = bc[lc[s] - half];
                 const f2 n2 = bc[lc[s] + half];
                 const f2 n3 = bc[lc[s]];
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
                     const float pa = __expf(-beta * dE);
                     const bool acc = u1 < pa;
-                    if (a.recheck && __builtin_fabsf(u1 - pa) < 1e-5f && ok[s]) {
+                    if (a.recheck && __builtin_fabsf(u1 - pa) < 1e-5f) {
                         const uint32_t idx = atomicAdd(&a.rq->count, 1u);
                         if (idx < a.rq->capacity) {
                             RecheckEntry e;
@@ -372,27 +376,24 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                         }
                     }
                     nv = acc ? prop : cur[s];
-                    nacc += (acc && ok[s]) ? 1ull : 0ull;
+                    nacc += acc ? 1ull : 0ull;
                 }
                 if constexpr (MEAS || KIND == kMeas) {
-                    if (ok[s]) {
-                        const f2 sc = sincos_turns(nv);
-                        // x neighbours: same j is +x when x is even (p = 0), -x otherwise
-                        const bool podd = ((ypar[s] + z) & 1) != 0;
-                        const f2 xp = podd ? n4 : n3, xm = podd ? n3 : n4;
-                        const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, ocm[s].c};
-                        const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, ocm[s].s};
-                        measure_site(acc, sc.c, sc.s, oc0[s].c, oc0[s].s, nc, ns);
-                    }
+                    const f2 sc = sincos_turns(nv);
+                    // x neighbours: same j is +x when x is even (p = 0), -x otherwise
+                    const bool podd = ((ypar[s] + z) & 1) != 0;
+                    const f2 xp = podd ? n4 : n3, xm = podd ? n3 : n4;
+                    const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, ocm[s].c};
+                    const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, ocm[s].s};
+                    measure_site(acc, sc.c, sc.s, oc0[s].c, oc0[s].s, nc, ns);
                 }
-                if constexpr (KIND != kMeas) {
-                    if (ok[s]) bstore(nv, rown, voff[s], sz);
-                }
+                if constexpr (KIND != kMeas) bstore(nv, rown, voff[s], sz);
             }
 
             // Plane z+1 into the other LDS buffer and rotate the z window.
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
+                if (!ok[s]) continue;
                 bn[lc[s]] = ocp[s];
                 ocm[s] = oc0[s];
                 oc0[s] = ocp[s];
@@ -400,10 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 cur[s] = pre_c[s];
             }
 #pragma unroll
-            for (int h = 0; h < HALO; ++h) {
-                const f2 v = sincos_turns(pre_h[h]);
-                if (hok[h]) bn[hl[h]] = v;
-            }
+            for (int h = 0; h < HALO; ++h)
+                if (hok[h]) bn[hl[h]] = sincos_turns(pre_h[h]);
             lds_barrier();
         };
 
@@ -588,52 +587,55 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             const bool store_a = zz >= 1 && zz <= TZ;
             const uint32_t sz = pb(z), szm = pb(z - 1);
             // a: colour 0 at plane z on tile and halo columns
+            // Work on columns past the tile (okT false) or past the halo rows
+            // (okH false) is skipped: with TY * L/2 not a multiple of the
+            // block size whole wavefronts have nothing to do in the last
+            // column, and the branch lets them skip it.
             f2 c0cur[SPT];
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
+                if (!okT[s]) continue;
                 const int lc = l1T(s), lx = lc + (par ? dxo[s] : dxe[s]);
                 const f2 n1 = p1[lc - half], n2 = p1[lc + half], n3 = p1[lc], n4 = p1[lx];
                 const f2 c1m = p1n[lc];
                 const float hx = ((c1m.c + c1p[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
                 const float hy = ((c1m.s + c1p[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
                 const float nv = overrelax_turns(t0[s], hx, hy);
-                if (store_a && okT[s]) bstore(nv, r0d, voffT[s], sz);
+                if (store_a) bstore(nv, r0d, voffT[s], sz);
                 c0cur[s] = sincos_turns(nv);
                 p0w[l0T(s)] = c0cur[s];
             }
-            {
+            if (okH) {
                 const int lx = par ? l1Hxo : l1Hxe;
                 const f2 n1 = p1[l1H - half], n2 = p1[l1H + half], n3 = p1[l1H], n4 = p1[lx];
                 const f2 hm = p1n[l1H];
                 const float hx = ((hm.c + hp.c) + (n1.c + n2.c)) + (n3.c + n4.c);
                 const float hy = ((hm.s + hp.s) + (n1.s + n2.s)) + (n3.s + n4.s);
-                const f2 hv = sincos_turns(overrelax_turns(ht0, hx, hy));
-                if (okH) p0w[l0H] = hv;
+                p0w[l0H] = sincos_turns(overrelax_turns(ht0, hx, hy));
             }
             // b: colour 1 at plane z-1 on tile columns (from the third step on)
             if (zz >= 2) {
 #pragma unroll
                 for (int s = 0; s < SPT; ++s) {
+                    if (!okT[s]) continue;
                     const int lc = l0T(s), lx = lc + (par ? dxo[s] : dxe[s]);
                     const f2 m1 = p0r[lc - half], m2 = p0r[lc + half], m3 = p0r[lc], m4 = p0r[lx];
                     const f2 c0m2 = p0r2[lc];
                     const float hx = ((c0m2.c + c0cur[s].c) + (m1.c + m2.c)) + (m3.c + m4.c);
                     const float hy = ((c0m2.s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
                     const float nv = overrelax_turns(r1m[s], hx, hy);
-                    if (okT[s]) bstore(nv, r1d, voffT[s], szm);
+                    bstore(nv, r1d, voffT[s], szm);
                     if constexpr (MEAS) {
-                        if (okT[s]) {
-                            // colour 1 at (y, z-1) has x = 2j + p, p = (y + z) & 1
-                            // (L even keeps the parity through the z wrap); the
-                            // same-j neighbour is +x when p = 0, -x when p = 1
-                            const bool podd = pz0[s] != (par != 0);
-                            const f2 xpv = podd ? m4 : m3, xmv = podd ? m3 : m4;
-                            const f2 sc = sincos_turns(nv);
-                            const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0m2.c};
-                            const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0m2.s};
-                            // m3 is the colour-0 site with the same storage index
-                            measure_site(acc, sc.c, sc.s, m3.c, m3.s, nc, ns);
-                        }
+                        // colour 1 at (y, z-1) has x = 2j + p, p = (y + z) & 1
+                        // (L even keeps the parity through the z wrap); the
+                        // same-j neighbour is +x when p = 0, -x when p = 1
+                        const bool podd = pz0[s] != (par != 0);
+                        const f2 xpv = podd ? m4 : m3, xmv = podd ? m3 : m4;
+                        const f2 sc = sincos_turns(nv);
+                        const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0m2.c};
+                        const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0m2.s};
+                        // m3 is the colour-0 site with the same storage index
+                        measure_site(acc, sc.c, sc.s, m3.c, m3.s, nc, ns);
                     }
                 }
             }
@@ -642,6 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
             lds_barrier();
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
+                if (!okT[s]) continue;
                 p1n[l1T(s)] = c1p[s];
                 c1p[s] = sincos_turns(preT1[s]);
                 r1m[s] = r1c[s];
@@ -649,13 +652,12 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
                 r1p[s] = preT1[s];
                 t0[s] = preT0[s];
             }
-            const f2 onext = sincos_turns(preO);
             if (okH) {
                 p1n[l1H] = hp;
-                p1n[l1O] = onext;
+                p1n[l1O] = sincos_turns(preO);
+                hp = sincos_turns(preH1);
+                ht0 = preH0;
             }
-            hp = sincos_turns(preH1);
-            ht0 = preH0;
             lds_barrier();
         };
 

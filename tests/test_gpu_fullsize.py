@@ -18,6 +18,7 @@ from gpu_util import circ, colour_mask, field_numpy
 pytestmark = pytest.mark.gpu
 
 L_BENCH, R_BENCH = 160, 32
+BENCH_TILING, BENCH_TILING_FUSED = (16, 20), (8, 40)
 
 
 def make(L, betas, seed, prec="fp32", start="random"):
@@ -29,9 +30,29 @@ def make(L, betas, seed, prec="fp32", start="random"):
 def bench_sim(gpu):
     betas = np.linspace(0.4538, 0.4546, R_BENCH)
     s = make(L_BENCH, [betas], 4)
-    s.set_tiling(0, 8, 20, 0)   # the launch shape bench.py times
+    s.set_tiling(0, *BENCH_TILING, 0)   # the launch shapes bench.py times
+    s.set_tiling_fused(0, *BENCH_TILING_FUSED)
     yield s, betas
     s.close()
+
+
+def test_full_size_fused_sweep_equals_half_sweeps(bench_sim):
+    """A whole sweep (1 + 10) in the benchmark's launch shapes, with the ten
+    over-relaxation substeps as five fused launches, leaves bit-for-bit the
+    configuration that the half-sweep kernels (checked site by site against
+    the oracle above) produce from the same state."""
+    import torch
+    from paper_1211_0780_amd.sim import Sim
+    s, betas = bench_sim
+    ref = Sim(L_BENCH, [betas], seed=4, prec="fp32", fused_or=False)
+    ref.set_tiling(0, *BENCH_TILING, 0)
+    ref.set_state(s.get_state())
+    s.sweep(1, 10)
+    ref.sweep(1, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(s.angles, ref.angles)
+    assert s.counters() == ref.counters()
+    ref.close()
 
 
 def test_full_size_over_relaxation_every_site(bench_sim):
