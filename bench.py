@@ -44,23 +44,23 @@ DEFAULT_TILING_FUSED = "8x40"
 def _oracle_one_sweep(args):
     """One sweep (1 Metropolis + 10 over-relaxation) of one L=160 configuration
     with the CPU oracle; returns (site-updates, seconds)."""
-    k, L_, beta, seed = args
+    k, L_, beta, seed, window = args
     import numpy as np
     import oracle
     th = oracle.init(L_, 1, seed, 0)
     t0 = time.perf_counter()
-    oracle.sweep(th, L_, np.array([beta]), seed, 0, 0, N_METRO, N_OR)
+    oracle.sweep(th, L_, np.array([beta]), seed, 0, 0, N_METRO, N_OR, window=window)
     dt = time.perf_counter() - t0
     return (N_METRO + N_OR) * L_ ** 3, dt
 
 
-def cpu_baseline():
+def cpu_baseline(window=0.0):
     import numpy as np
     import oracle
     oracle.build()
     cores = max(1, min(16, os.cpu_count() or 1, R))
     betas = np.linspace(BETA_LO, BETA_HI, R)
-    jobs = [(k, L, float(betas[k]), SEED) for k in range(cores)]
+    jobs = [(k, L, float(betas[k]), SEED, window) for k in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_oracle_one_sweep, jobs)
@@ -74,9 +74,16 @@ def cpu_baseline():
         "kind": "oracle",
         "sample": f"{cores} configurations of L={L} (one per process), one sweep of "
                   f"{N_METRO} Metropolis + {N_OR} over-relaxation each, beta in "
-                  f"[{BETA_LO}, {BETA_HI}]; rate over the slowest process's sweep time "
+                  f"[{BETA_LO}, {BETA_HI}], {proposal_text(window)}; rate over the slowest "
+                  "process's sweep time "
                   f"({busy:.1f} s; wall {wall:.1f} s incl. start-up)",
     }
+
+
+def proposal_text(window):
+    if window > 0:
+        return f"restricted-window Metropolis proposal theta + {window:g} (U - 1/2)"
+    return "uniform Metropolis proposal"
 
 
 def kernel_source_hash():
@@ -182,6 +189,9 @@ def main():
                          "so that timing and counter runs use the same launch shape)")
     ap.add_argument("--tiling-fused", default=DEFAULT_TILING_FUSED,
                     help="'TYxTZ' for the fused over-relaxation kernel (ignored with --tiling auto)")
+    ap.add_argument("--window", type=float, default=0.0,
+                    help="restricted-window Metropolis proposal theta + W (U - 1/2), 0 < W <= 2 pi "
+                         "(default 0: uniform proposal on the circle)")
     ap.add_argument("--unfused", action="store_true",
                     help="run over-relaxation as two half-sweep kernels per substep")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -219,6 +229,8 @@ def main():
             sim.set_tiling_fused(0, ty2, tz2)
         tiling = sim.get_tiling(0)
     tiling_fused = sim.get_tiling_fused(0)
+    if args.window > 0:
+        sim.set_proposal_window(args.window)
     if args.traffic_probe:
         traffic_probe(sim, dev)
         return
@@ -233,12 +245,14 @@ def main():
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    acc0 = sim.metro_accepts()
     t0 = time.perf_counter()
     ev0.record(stream)
     sim.run(args.steps, N_METRO, N_OR, exchange_every=1, obs=obs)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    acceptance = float((sim.metro_accepts() - acc0).sum()) / (args.steps * N_METRO * N * R)
 
     # per-kernel device time: HIP events on the sweep's stream around each group
     # of consecutive launches of one kind (group time / launches in the group).
@@ -303,7 +317,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(args.window)
 
     line = {
         "metric": METRIC,
@@ -322,8 +336,10 @@ def main():
             "workload": f"L={L} periodic cubic XY lattice x {R} parallel-tempering replicas, "
                         f"beta linspace [{BETA_LO}, {BETA_HI}], float32 angles, float64 "
                         f"reductions and exchange, sweep = {N_METRO} Metropolis + {N_OR} "
-                        "over-relaxation, measurement and exchange every sweep, random start",
+                        f"over-relaxation, {proposal_text(args.window)}, measurement and "
+                        "exchange every sweep, random start",
             "L": L, "replicas": R, "n_metro": N_METRO, "n_or": N_OR, "seed": SEED,
+            "proposal_window": args.window,
             "site_updates_per_step": (N_METRO + N_OR) * N * R,
             "tiling": {"ty": tiling[0], "tz": tiling[1], "grid_cap": tiling[2]},
             "tiling_fused": {"ty": tiling_fused[0], "tz": tiling_fused[1]},
@@ -335,6 +351,7 @@ def main():
             "note": f"plain one-thread-per-site float64 kernels, L={L}, 1 replica, same sweep",
             "hbm_frac_at_24B": round(fp64_rate * BYTES_PER_UPDATE_F64 / 1e9 / HBM_PEAK_GBS, 4),
         },
+        "metropolis_acceptance": round(acceptance, 5),
         "wall_s_timed": wall,
     }
     print(json.dumps(line), flush=True)
