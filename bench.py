@@ -273,6 +273,7 @@ def main():
     if not np.all(np.isfinite(o)):
         raise SystemExit("non-finite observables")
     avg = {k: (tot[k] / cnt[k] if cnt[k] else None) for k in tot}
+    overflow = sim.recheck_overflow()
     khash = kernel_source_hash()
     if cnt["over_fused"]:
         kname, kms = "fused over-relaxation substep (k_or2_f32: both colours per launch)", avg["over_fused"]
@@ -352,6 +353,7 @@ def main():
             "hbm_frac_at_24B": round(fp64_rate * BYTES_PER_UPDATE_F64 / 1e9 / HBM_PEAK_GBS, 4),
         },
         "metropolis_acceptance": round(acceptance, 5),
+        "recheck_overflow": overflow,
         "wall_s_timed": wall,
     }
     print(json.dumps(line), flush=True)

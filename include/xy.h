@@ -233,6 +233,19 @@ xy_status xy_get_permutation(xy_ctx ctx, int32_t lattice, int32_t *slot);
 xy_status xy_get_metro_accepts(xy_ctx ctx, int64_t *n_acc);
 
 /*
+ * Float64 re-decision queue of the FP32 Metropolis path (Sec. II; the
+ * acceptance test of the Metropolis update): sites whose float32 decision
+ * lies within 1e-5 of the threshold are queued and decided again in float64.
+ * The queue holds max(4096, min(2^22, S / 1000)) entries, S being the sites
+ * one half-sweep updates over every lattice and replica (about 2e-5 S land
+ * in the band); entries beyond that keep their float32 decision and are
+ * counted.  *n receives the cumulative count since
+ * xy_init (0 for FP64 contexts and with XY_F_NO_RECHECK).  Waits for the
+ * stream.
+ */
+xy_status xy_get_recheck_overflow(xy_ctx ctx, uint64_t *n);
+
+/*
  * Launch shape of the FP32 tiled half-sweep for one lattice: a work item is
  * ty rows (y) by L/2 sites (x) of one colour, streamed over tz planes (z).
  * ty and tz must divide L, ty*L/2 <= 2048.  grid_cap > 0 makes the launch

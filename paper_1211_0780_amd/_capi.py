@@ -23,7 +23,7 @@ EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange"
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
            "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused",
-           "xy_set_proposal_window"]
+           "xy_set_proposal_window", "xy_get_recheck_overflow"]
 
 
 class XYConfig(ctypes.Structure):
@@ -83,6 +83,8 @@ def lib():
         L.xy_get_permutation.restype = i32
         L.xy_get_metro_accepts.argtypes = [vp, i64p]
         L.xy_get_metro_accepts.restype = i32
+        L.xy_get_recheck_overflow.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.xy_get_recheck_overflow.restype = i32
         L.xy_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
         L.xy_get_state.restype = i32
         L.xy_set_state.argtypes = [vp, vp, ctypes.c_size_t]

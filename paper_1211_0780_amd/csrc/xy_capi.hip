@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -1140,6 +1141,18 @@ xy_status xy_get_metro_accepts(xy_ctx c, int64_t *n_acc)
                              hipMemcpyDeviceToHost, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < c->R_total; ++i) n_acc[i] = (int64_t)v[i];
+    return XY_OK;
+}
+
+xy_status xy_get_recheck_overflow(xy_ctx c, uint64_t *n)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!n) return fail(c, XY_ERR_ARG, "n is NULL");
+    uint32_t v = 0;
+    XY_HIP(c, hipMemcpyAsync(&v, (const char *)c->d_rq + offsetof(RecheckQueue, overflow), sizeof(v),
+                             hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    *n = v;
     return XY_OK;
 }
 

@@ -186,6 +186,14 @@ class Sim:
         C.check(C.lib().xy_get_metro_accepts(self._ctx, acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self._ctx)
         return acc
 
+    def recheck_overflow(self):
+        """Near-threshold Metropolis decisions that did not fit the float64
+        re-decision queue since the context was created (they kept their
+        float32 decision)."""
+        n = ctypes.c_uint64()
+        C.check(C.lib().xy_get_recheck_overflow(self._ctx, ctypes.byref(n)), self._ctx)
+        return n.value
+
     def swap_accepts(self):
         """Cumulative accepted exchanges of pair (p, p+1) per position index."""
         acc = np.zeros(self.R_total, dtype=np.int64)

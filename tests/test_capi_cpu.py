@@ -87,6 +87,24 @@ def test_null_context_calls_fail_cleanly(xylib):
     xylib.xy_destroy(None)
 
 
+def test_every_context_entry_point_rejects_a_null_context(xylib):
+    """Every entry point whose first argument is the context returns
+    XY_ERR_ARG for NULL, whatever the other arguments are."""
+    skip = {"xy_angles_bytes", "xy_init", "xy_last_error", "xy_destroy"}
+    checked = 0
+    for name in C.EXPORTS:
+        if name in skip:
+            continue
+        fn = getattr(xylib, name)
+        nargs = len(fn.argtypes)
+        args = [None] + [None if t in (ctypes.c_void_p,) or hasattr(t, "contents") or t is ctypes.c_char_p
+                         else 0 for t in fn.argtypes[1:]]
+        assert len(args) == nargs
+        assert fn(*args) == C.XY_ERR_ARG, name
+        checked += 1
+    assert checked == len(C.EXPORTS) - len(skip)
+
+
 def test_angle_bytes(xylib):
     assert xylib.xy_angles_bytes(ctypes.byref(_cfg([8], [3], [0.1, 0.2, 0.3]))) == 3 * 512 * 4
     assert xylib.xy_angles_bytes(ctypes.byref(_cfg([8, 4], [1, 2], [0.1, 0.2, 0.3],

@@ -100,6 +100,7 @@ def test_full_size_metropolis_every_site(bench_sim):
         dE = (np.cos(before[i]) - np.cos(prop)) * hx[i] + (np.sin(before[i]) - np.sin(prop)) * hy[i]
         assert abs(u - np.exp(-betas[k] * dE)) < 1e-6
     assert bad.size <= 5
+    assert s.recheck_overflow() == 0
 
 
 def test_full_size_measurement(bench_sim):

@@ -157,6 +157,9 @@ def test_autotune_leaves_the_chain_untouched(gpu):
     (12, [0.45], (12, 12)),          # one tile per slot: halo rows and planes wrap onto the tile
     (10, [0.3, 0.5], (2, 5)),
     (160, [0.4542], (5, 20)),        # the benchmark lattice
+    (160, [0.4542], (16, 20)),       # five columns per thread
+    (64, [0.44, 0.46], (32, 8)),     # four columns per thread
+    (48, [0.45], (48, 6)),           # one tile per slot in y, five columns per thread
 ])
 def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     """The fused substep performs the same float32 operations in the same
@@ -212,3 +215,19 @@ def test_profiled_sweep_equals_sweep(gpu, fused):
     nf = 4 if fused else 0
     assert n == {"metro": 2, "over": 2 * (5 - nf), "over_fused": nf, "other": 1}
     assert all(ms[k] > 0 for k in n if n[k]) and all(ms[k] == 0 for k in n if not n[k])
+
+
+def test_fused_batch_with_mixed_tiles_equals_half_sweeps(gpu):
+    """One fused launch covers every lattice of a batch: the largest tile sets
+    the columns per thread of the launch, also for lattices with small tiles."""
+    from paper_1211_0780_amd.sim import Sim
+    L = [64, 16, 10]
+    betas = [[0.44, 0.46], [0.45], [0.40, 0.50]]
+    a = Sim(L, betas, seed=29, prec="fp32", fused_or=True)
+    b = Sim(L, betas, seed=29, prec="fp32", fused_or=False)
+    a.set_tiling_fused(0, 32, 8)
+    for sweep in range(2):
+        a.sweep(1, 4)
+        b.sweep(1, 4)
+        torch.cuda.synchronize()
+        assert torch.equal(a.angles, b.angles), sweep
