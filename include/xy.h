@@ -64,7 +64,7 @@ typedef enum {
     XY_ERR_OOM = 3,         /* device or host allocation failed */
     XY_ERR_HIP = 4,         /* a HIP runtime call failed; the message names it */
     XY_ERR_STATE = 5,       /* state blob or device state inconsistent (bad blob, NaN angle) */
-    XY_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+    XY_ERR_UNSUPPORTED = 6  /* valid request this library does not implement */
 } xy_status;
 
 typedef enum {

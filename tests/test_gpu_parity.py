@@ -152,7 +152,7 @@ def test_half_sweep_parity(gpu, prec, L, R, tiling):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_full_sweeps_match_oracle(gpu, prec):
-    """configs[0]-like chain (L = 8, beta = 0.4542, 1 + 1): ten sweeps, each
+    """The single-lattice FP64 chain (L = 8, beta = 0.4542, 1 + 1): ten sweeps, each
     re-started from the GPU state, against the oracle's sweep."""
     L, seed, beta = 8, 1, 0.4542
     s = make(L, [beta], seed, prec)

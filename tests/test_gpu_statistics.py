@@ -1,6 +1,6 @@
 """Long-run statistical parity (same equilibrium law) on the GPU.
 
-GPU chains against the oracle's chain (configs[0]-like single lattice, and a
+GPU chains against the oracle's chain (the L = 8 single lattice, and a
 small parallel-tempering ladder), float32 against float64 kernels on the
 same ladders, exchange on against off, and the Binder crossing of the
 batched finite-size-scaling set.  The two chains of a comparison always run
@@ -85,7 +85,7 @@ def test_exchange_does_not_change_equilibrium(gpu):
 
 
 def test_fp32_matches_fp64_on_a_ladder(gpu):
-    """configs[2]-like: L = 64, 32 replicas over [0.4530, 0.4554], 1 + 8,
+    """The L = 64 ladder: 32 replicas over [0.4530, 0.4554], 1 + 8,
     float32 (with float64 near-threshold re-decision) against the all-float64
     kernels, both with exchange every sweep, from independent seeds (with a
     shared seed the two chains would stay correlated and the comparison would
@@ -101,7 +101,7 @@ def test_fp32_matches_fp64_on_a_ladder(gpu):
 
 
 def test_fss_batch_binder_crossing(gpu):
-    """configs[4]: L in {24, 32, 48, 64, 96, 128}, 16 replicas each over
+    """The batched finite-size-scaling set: L in {24, 32, 48, 64, 96, 128}, 16 replicas each over
     [0.452, 0.456], one launch per half-sweep for the whole batch, graph
     replayed, autotuned tiles.  Sec. III: U_L curves cross at
     beta_c = 1/2.2019 = 0.45415, inside the ladder: the smallest lattice has
