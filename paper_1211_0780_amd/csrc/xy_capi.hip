@@ -502,6 +502,43 @@ xy_status relayout(xy_ctx c)
     return XY_OK;
 }
 
+// Device time of one call of `launch`, averaged over `reps` calls after one
+// warm-up call, on the context's stream.
+template <class F>
+xy_status time_launches(xy_ctx c, hipEvent_t e0, hipEvent_t e1, int reps, F &&launch, double *ms)
+{
+    xy_status st = launch();
+    if (st) return st;
+    XY_HIP(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r)
+        if ((st = launch())) return st;
+    XY_HIP(c, hipEventRecord(e1, c->stream));
+    XY_HIP(c, hipEventSynchronize(e1));
+    float t = 0.f;
+    XY_HIP(c, hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / reps;
+    return XY_OK;
+}
+
+// Candidate tile shapes of one lattice: ty and tz divide L, at least half a
+// block of sites per plane (unless the tile is the whole plane), at most 2048,
+// and z-chunks of 2..64 planes (or the whole lattice).
+std::vector<std::pair<int, int>> tile_candidates(int L)
+{
+    const int half = L / 2;
+    std::vector<std::pair<int, int>> out;
+    for (int ty : divisors(L)) {
+        if (ty * half > 8 * kBlock) continue;
+        if (ty * half < kBlock / 2 && ty != L) continue;  // mostly idle lanes
+        for (int tz : divisors(L)) {
+            if (tz < 2 && L > 2) continue;
+            if (tz > 64 && tz != L) continue;
+            out.push_back({ty, tz});
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -830,187 +867,93 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
     if (n_metro < 0 || n_or < 0 || n_metro + n_or < 1 || reps < 1 || reps > 100)
         return fail(c, XY_ERR_ARG, "need n_metro, n_or >= 0, n_metro + n_or >= 1, 1 <= reps <= 100");
     XY_HIP(c, hipStreamSynchronize(c->stream));
-    LatDev *d_one = nullptr;
+    // Every lattice of a batch shares one launch, so each candidate is timed
+    // on the whole batch: coordinate descent, one lattice at a time, the
+    // others keeping their current tiles.  The Metropolis and over-relaxation
+    // half-sweeps modify the configuration and the acceptance counters, which
+    // are saved first and restored at the end; the fused kernel only writes
+    // the second buffer.
     void *save = nullptr;
     unsigned long long *save_acc = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t bytes = (size_t)c->n_elems * c->elem;
     xy_status st = XY_OK;
-    size_t max_bytes = 0;
-    for (int l = 0; l < c->n_lat; ++l)
-        max_bytes = std::max(max_bytes, (size_t)c->R[l] * (size_t)c->lat_sweep[l].N * c->elem);
-    if ((st = dev_alloc(c, &d_one, 1)) || (st = dev_alloc(c, (char **)&save, max_bytes)) ||
-        (st = dev_alloc(c, &save_acc, c->R_total))) {
-        (void)hipFree(d_one);
+    if ((st = dev_alloc(c, (char **)&save, bytes)) || (st = dev_alloc(c, &save_acc, c->R_total))) {
         (void)hipFree(save);
         (void)hipFree(save_acc);
         return st;
     }
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         st = fail(c, XY_ERR_HIP, "hipEventCreate failed");
-    if (!st && hipMemcpyAsync(save_acc, c->d_macc, sizeof(unsigned long long) * c->R_total,
-                              hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        st = fail(c, XY_ERR_HIP, "saving counters failed");
-    for (int l = 0; l < c->n_lat && !st; ++l) {
-        const LatDev &base = c->lat_sweep[l];
-        const int L = base.L, half = base.half;
-        char *lat_ang = (char *)c->ang + (size_t)base.base * c->elem;
-        const size_t bytes = (size_t)base.R * (size_t)base.N * c->elem;
-        if (hipMemcpyAsync(save, lat_ang, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
-            st = fail(c, XY_ERR_HIP, "saving angles failed");
-            break;
+    if (!st && (hipMemcpyAsync(save, c->ang, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                hipMemcpyAsync(save_acc, c->d_macc, sizeof(unsigned long long) * c->R_total,
+                               hipMemcpyDeviceToDevice, c->stream) != hipSuccess))
+        st = fail(c, XY_ERR_HIP, "saving the state failed");
+    const int grid_cap = c->grid_sweep;
+    const int w_metro = n_metro, w_over = n_or - fused_substeps(c, n_or);
+    auto half_cost = [&](double *cost) -> xy_status {
+        *cost = 0.0;
+        for (int kind = 0; kind < 2; ++kind) {
+            const int weight = kind == 0 ? w_metro : w_over;
+            if (weight == 0) continue;
+            double ms = 0.0;
+            xy_status s2 = time_launches(c, e0, e1, reps,
+                                         [&] { return launch_half(c, kind == 0 ? kMetro : kOver, 0, 0, false); }, &ms);
+            if (s2) return s2;
+            *cost += weight * ms;
         }
+        return XY_OK;
+    };
+    for (int l = 0; l < c->n_lat && !st && (w_metro + w_over) > 0; ++l) {
         Tiling best = c->tiles[l];
         double best_cost = 1e300;
-        for (int ty : divisors(L)) {
-            if (ty * half > 8 * kBlock) continue;
-            if (ty * half < kBlock / 2 && ty != L) continue;  // mostly idle lanes
-            for (int tz : divisors(L)) {
-                if (tz < 2 && L > 2) continue;
-                if (tz > 64 && tz != L) continue;
-                Tiling t;
-                t.TY = ty;
-                t.TZ = tz;
-                t.spt = spt_for(ty * half);
-                LatDev one = base;
-                one.TY = ty;
-                one.TZ = tz;
-                one.ny = L / ty;
-                one.nz = L / tz;
-                one.items_per_slot = one.ny * one.nz;
-                one.item_base = 0;
-                const int items = one.R * one.items_per_slot;
-                if ((size_t)kPartials * items > c->partials_cap) continue;
-                if (hipMemcpyAsync(d_one, &one, sizeof(LatDev), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-                    st = fail(c, XY_ERR_HIP, "upload failed");
+        for (const auto &cand : tile_candidates(c->L[l])) {
+            if (xy_set_tiling(c, l, cand.first, cand.second, grid_cap) != XY_OK) continue;
+            double cost = 0.0;
+            if ((st = half_cost(&cost))) break;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = c->tiles[l];
+            }
+        }
+        if (st) break;
+        c->tiles[l] = best;
+        st = relayout(c);
+    }
+    if (!st && c->fused_or && n_or >= 2) {
+        for (int l = 0; l < c->n_lat && !st; ++l) {
+            Tiling best = c->tiles2[l];
+            double best_ms = 1e300;
+            for (const auto &cand : tile_candidates(c->L[l])) {
+                if (xy_set_tiling_fused(c, l, cand.first, cand.second) != XY_OK) continue;
+                double ms = 0.0;
+                if ((st = time_launches(c, e0, e1, reps, [&] { return launch_or2(c, c->ang, c->ang2, false); },
+                                        &ms)))
                     break;
-                }
-                SweepArgs a{};
-                a.lats = d_one;
-                a.n_lat = 1;
-                a.total_items = items;
-                a.ang = c->ang;
-                a.beta = c->d_beta;
-                a.pos = c->d_pos;
-                a.ctl = c->d_ctl;
-                a.k0 = c->k0;
-                a.k1 = c->k1;
-                a.colour = 0;
-                a.substep = 0;
-                a.recheck = 0;
-                a.rq = c->d_rq;
-                a.partials = c->d_partials;
-                a.macc = c->d_macc;
-                const size_t lds = (size_t)2 * (ty + 2) * half * 2 * sizeof(float);
-                const int halo = (L > kBlock) ? 4 : 1;
-                double cost = 0.0;
-                for (int kind = 0; kind < 2 && !st; ++kind) {
-                    // over-relaxation substeps that run fused do not use this kernel
-                    const int weight = kind == 0 ? n_metro : n_or - fused_substeps(c, n_or);
-                    if (weight == 0) continue;
-                    const int kk = kind == 0 ? kMetro : kOver;
-                    hipError_t e = launch_tile_f32(kk, false, t.spt, halo, items, lds, a, c->stream);  // warm
-                    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-                    for (int r = 0; r < reps && e == hipSuccess; ++r)
-                        e = launch_tile_f32(kk, false, t.spt, halo, items, lds, a, c->stream);
-                    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (e != hipSuccess) {
-                        st = fail(c, XY_ERR_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
-                        break;
-                    }
-                    cost += (double)weight * ms / reps;
-                }
-                if (st) break;
-                if (cost < best_cost) {
-                    best_cost = cost;
-                    best = t;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c->tiles2[l];
                 }
             }
             if (st) break;
-        }
-        if (hipMemcpyAsync(lat_ang, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess && !st)
-            st = fail(c, XY_ERR_HIP, "restoring angles failed");
-        if (!st) c->tiles[l] = best;
-    }
-    if (hipMemcpyAsync(c->d_macc, save_acc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToDevice,
-                       c->stream) != hipSuccess && !st)
-        st = fail(c, XY_ERR_HIP, "restoring counters failed");
-    // Fused over-relaxation tiles: the kernel reads the configuration and
-    // writes the second buffer only, so timing it leaves the chain untouched.
-    if (!st && c->fused_or && n_or >= 2) {
-        for (int l = 0; l < c->n_lat && !st; ++l) {
-            const LatDev &base = c->lat_sweep[l];
-            const int L = base.L, half = base.half;
-            Tiling best = c->tiles2[l];
-            double best_ms = 1e300;
-            for (int ty : divisors(L)) {
-                if (ty * half > 4 * kBlock) continue;
-                if (ty * half < kBlock / 2 && ty != L) continue;
-                for (int tz : divisors(L)) {
-                    if (tz < 2 && L > 2) continue;
-                    if (tz > 64 && tz != L) continue;
-                    Tiling t;
-                    t.TY = ty;
-                    t.TZ = tz;
-                    t.spt = spt_for(ty * half);
-                    LatDev one = base;
-                    one.TY = ty;
-                    one.TZ = tz;
-                    one.ny = L / ty;
-                    one.nz = L / tz;
-                    one.items_per_slot = one.ny * one.nz;
-                    one.item_base = 0;
-                    const int items = one.R * one.items_per_slot;
-                    if (hipMemcpyAsync(d_one, &one, sizeof(LatDev), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-                        st = fail(c, XY_ERR_HIP, "upload failed");
-                        break;
-                    }
-                    SweepArgs a{};
-                    a.lats = d_one;
-                    a.n_lat = 1;
-                    a.total_items = items;
-                    a.ang = c->ang;
-                    a.ang_dst = c->ang2;
-                    a.beta = c->d_beta;
-                    a.pos = c->d_pos;
-                    a.ctl = c->d_ctl;
-                    a.partials = c->d_partials;
-                    a.macc = c->d_macc;
-                    a.rq = c->d_rq;
-                    const size_t lds = (size_t)(2 * (ty + 4) + 3 * (ty + 2)) * half * 2 * sizeof(float);
-                    if (lds > kMaxLds) continue;
-                    hipError_t e = launch_or2_f32(false, t.spt, items, lds, a, c->stream);
-                    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-                    for (int r = 0; r < reps && e == hipSuccess; ++r)
-                        e = launch_or2_f32(false, t.spt, items, lds, a, c->stream);
-                    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (e != hipSuccess) {
-                        st = fail(c, XY_ERR_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
-                        break;
-                    }
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = t;
-                    }
-                }
-                if (st) break;
-            }
-            if (!st) c->tiles2[l] = best;
+            c->tiles2[l] = best;
+            st = relayout(c);
         }
     }
     (void)hipStreamSynchronize(c->stream);
+    if (hipMemcpyAsync(c->ang, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_macc, save_acc, sizeof(unsigned long long) * c->R_total, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (!st) st = fail(c, XY_ERR_HIP, "restoring the state failed");
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(d_one);
     (void)hipFree(save);
     (void)hipFree(save_acc);
-    if (st) return st;
-    return relayout(c);
+    free_graphs(c);  // captured launches carry the old shapes
+    c->e_fresh = c->bonds_fresh = false;
+    return st;
 }
 
 xy_status xy_set_tiling(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap)
