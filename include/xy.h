@@ -257,13 +257,18 @@ xy_status xy_get_recheck_overflow(xy_ctx ctx, uint64_t *n);
 xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int32_t grid_cap);
 
 /*
- * Pick (ty, tz) per lattice by timing: for every admissible tiling, reps
- * launches of one Metropolis and one over-relaxation half-sweep of that
- * lattice alone, cost = n_metro * t_metro + n_or * t_over; the cheapest is
- * kept.  The lattice's angles and acceptance counters are saved and restored
- * around the timing (the chain is unchanged), and near-threshold float64
- * re-decisions are off while timing.  Needs scratch device memory the size
- * of the largest lattice's angles.  No-op for FP64 contexts.  Waits.
+ * Pick the tile shapes of every lattice by timing.  All lattices of a
+ * context share one launch per half-sweep, so each candidate (ty, tz) of one
+ * lattice is timed on the whole batch while the other lattices keep their
+ * current shapes, one lattice after another (coordinate descent): first the
+ * half-sweep tiles, cost = n_metro * t_metro + n_unfused * t_over per launch
+ * of one Metropolis and one over-relaxation half-sweep (n_unfused: the
+ * over-relaxation substeps that do not run fused), then, when n_or >= 2 and
+ * the context fuses over-relaxation, the fused tiles, cost = one fused
+ * substep.  Each timing is reps launches after one warm-up launch.  The
+ * angles and acceptance counters are saved and restored around the timing,
+ * so the chain is unchanged.  Needs scratch device memory the size of the
+ * angle buffer.  No-op for FP64 contexts.  Waits.
  */
 xy_status xy_autotune(xy_ctx ctx, int32_t n_metro, int32_t n_or, int32_t reps);
 xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
