@@ -55,6 +55,25 @@ def test_full_size_fused_sweep_equals_half_sweeps(bench_sim):
     ref.close()
 
 
+def test_full_size_fused_measurement(bench_sim):
+    """The measurement fused into the last over-relaxation launch of a
+    graph-replayed sweep (the benchmark's path) against the standalone
+    measurement kernel on the same configurations and against the oracle."""
+    import torch
+    s, betas = bench_sim
+    N = L_BENCH ** 3
+    obs = torch.zeros((1, R_BENCH, 5), dtype=torch.float64, device="cuda")
+    s.run(1, 1, 10, exchange_every=0, obs=obs)
+    torch.cuda.synchronize()
+    fused = obs[0].cpu().numpy()
+    standalone = s.measure()
+    assert np.allclose(fused, standalone, rtol=1e-12, atol=1e-6)
+    for k in (0, R_BENCH - 1):
+        ref = oracle.measure(s.get_angles(0, k), L_BENCH)
+        assert abs(fused[k, 0] - ref[0]) <= 1e-6 * N
+        assert abs(fused[k, 2] - ref[2]) <= 1e-6
+
+
 def test_full_size_over_relaxation_every_site(bench_sim):
     s, betas = bench_sim
     L = L_BENCH
