@@ -268,10 +268,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 
         // Prologue.  Converted: other colour at z0-1, z0, z0+1; raw (in flight
         // one plane ahead of use): other colour at z0+2, ours at z0+1, halo
-        // at z0+1.  Plane z0 of the other colour (tile and halo) goes to LDS.
+        // at z0+1.  Plane z0 of the other colour (tile and halo) goes to the
+        // LDS buffer of the first step, plane z0-1 (tile columns only) to the
+        // other one: a column's z-1 neighbour is read back from there, and
+        // only its z+1 neighbour is held in registers.
         auto wrapz = [L](int z) { return z >= L ? z - L : z; };
         const int zm1 = (z0 == 0) ? L - 1 : z0 - 1;
-        f2 ocm[SPT], oc0[SPT], ocp[SPT];
+        f2 ocp[SPT];
         float cur[SPT];
         float a_o[SPT], a_c[SPT], a_h[HALO], b_o[SPT], b_c[SPT], b_h[HALO];
         int lx_even[SPT], lx_odd[SPT];  // LDS index of the x-neighbour on even / odd steps
@@ -280,13 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
             const bool p_even = ((ypar[s] + z0) & 1) != 0;
             lx_even[s] = p_even ? lxp[s] : lxm[s];
             lx_odd[s] = p_even ? lxm[s] : lxp[s];
-            ocm[s] = sincos_turns(bload(roth, voff[s], (uint32_t)zm1 * plane_b));
-            oc0[s] = sincos_turns(bload(roth, voff[s], (uint32_t)z0 * plane_b));
+            const f2 om = sincos_turns(bload(roth, voff[s], (uint32_t)zm1 * plane_b));
+            const f2 o0 = sincos_turns(bload(roth, voff[s], (uint32_t)z0 * plane_b));
             ocp[s] = sincos_turns(bload(roth, voff[s], (uint32_t)wrapz(z0 + 1) * plane_b));
             cur[s] = bload(rown, voff[s], (uint32_t)z0 * plane_b);
             a_o[s] = bload(roth, voff[s], (uint32_t)wrapz(z0 + 2) * plane_b);
             a_c[s] = bload(rown, voff[s], (uint32_t)wrapz(z0 + 1) * plane_b);
-            buf0[lc[s]] = oc0[s];
+            buf0[lc[s]] = o0;
+            buf1[lc[s]] = om;
         }
 #pragma unroll
         for (int h = 0; h < HALO; ++h) {
@@ -339,8 +343,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 const f2 n2 = bc[lc[s] + half];
                 const f2 n3 = bc[lc[s]];
                 const f2 n4 = bc[lx[s]];
-                const float hx = ((ocm[s].c + ocp[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
-                const float hy = ((ocm[s].s + ocp[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
+                // plane z-1 of this column: still in the other buffer, which
+                // this lane overwrites with plane z+1 only at the end of the step
+                const f2 om = bn[lc[s]];
+                const float hx = ((om.c + ocp[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
+                const float hy = ((om.s + ocp[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
                 float nv = cur[s];
                 if constexpr (KIND == kOver) {
                     nv = overrelax_turns(cur[s], hx, hy);
@@ -383,20 +390,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     // x neighbours: same j is +x when x is even (p = 0), -x otherwise
                     const bool podd = ((ypar[s] + z) & 1) != 0;
                     const f2 xp = podd ? n4 : n3, xm = podd ? n3 : n4;
-                    const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, ocm[s].c};
-                    const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, ocm[s].s};
-                    measure_site(acc, sc.c, sc.s, oc0[s].c, oc0[s].s, nc, ns);
+                    const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, om.c};
+                    const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, om.s};
+                    // n3 is the other-colour site with the same storage index
+                    measure_site(acc, sc.c, sc.s, n3.c, n3.s, nc, ns);
                 }
                 if constexpr (KIND != kMeas) bstore(nv, rown, voff[s], sz);
             }
 
-            // Plane z+1 into the other LDS buffer and rotate the z window.
+            // Plane z+1 into the other LDS buffer; plane z+2 into registers.
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
                 if (!ok[s]) continue;
                 bn[lc[s]] = ocp[s];
-                ocm[s] = oc0[s];
-                oc0[s] = ocp[s];
                 ocp[s] = sincos_turns(pre_o[s]);
                 cur[s] = pre_c[s];
             }
