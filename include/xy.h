@@ -248,8 +248,12 @@ xy_status xy_get_recheck_overflow(xy_ctx ctx, uint64_t *n);
 /*
  * Launch shape of the FP32 tiled half-sweep for one lattice: a work item is
  * ty rows (y) by L/2 sites (x) of one colour, streamed over tz planes (z).
- * ty and tz must divide L, ty*L/2 <= 2048.  grid_cap > 0 makes the launch
- * persistent with at most grid_cap workgroups (0: one workgroup per item).
+ * ty and tz must divide L, ty*L/2 <= 2048.  Launches are persistent: each
+ * workgroup takes work items in turn.  grid_cap > 0 sets the number of
+ * workgroups (at most one per item); grid_cap = 0 (the default) uses as many
+ * as the GPU holds at once, compute units times the kernel's resident
+ * workgroups per CU.  The cap applies to the half-sweep and the fused
+ * over-relaxation launches.
  * Results do not depend on these choices (they only change the order in
  * which independent same-colour sites are visited); they exist for tuning.
  * XY_ERR_UNSUPPORTED for FP64 contexts.  Takes effect for later calls.

@@ -75,10 +75,12 @@ struct SweepArgs {
 };
 
 // Launchers (stream-ordered, no synchronisation).
+// With per_cu non-null the tiled launchers launch nothing and report in
+// *per_cu how many workgroups of the selected kernel fit on one CU.
 hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid,
-                           size_t lds_bytes, const SweepArgs &a, hipStream_t s);
+                           size_t lds_bytes, const SweepArgs &a, hipStream_t s, int *per_cu = nullptr);
 hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
-                          hipStream_t s);
+                          hipStream_t s, int *per_cu = nullptr);
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
                           int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);

@@ -973,65 +973,78 @@ __global__ void k_tick(Ctl *ctl, uint32_t dt, uint32_t dtau, uint32_t dring, int
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launchers.  With per_cu set, nothing is launched: *per_cu receives how many
+// workgroups of the selected kernel fit on one CU at the given LDS size (the
+// resident capacity that persistent launches are sized to).
 // ---------------------------------------------------------------------------
+typedef void (*SweepKernel)(SweepArgs);
+
+static hipError_t launch_or_query(SweepKernel k, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
+                                  int *per_cu)
+{
+    if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kBlock, lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
 template <int KIND, bool MEAS, int HALO>
-static hipError_t launch_tile_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s)
+static hipError_t launch_tile_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
+                                  int *per_cu)
 {
     switch (spt) {
-    case 1: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 1, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 2, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 3, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 4, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 5, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 6: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 6, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_tile_f32<KIND, MEAS, 8, HALO>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 1: return launch_or_query(k_tile_f32<KIND, MEAS, 1, HALO>, grid, lds, a, s, per_cu);
+    case 2: return launch_or_query(k_tile_f32<KIND, MEAS, 2, HALO>, grid, lds, a, s, per_cu);
+    case 3: return launch_or_query(k_tile_f32<KIND, MEAS, 3, HALO>, grid, lds, a, s, per_cu);
+    case 4: return launch_or_query(k_tile_f32<KIND, MEAS, 4, HALO>, grid, lds, a, s, per_cu);
+    case 5: return launch_or_query(k_tile_f32<KIND, MEAS, 5, HALO>, grid, lds, a, s, per_cu);
+    case 6: return launch_or_query(k_tile_f32<KIND, MEAS, 6, HALO>, grid, lds, a, s, per_cu);
+    case 8: return launch_or_query(k_tile_f32<KIND, MEAS, 8, HALO>, grid, lds, a, s, per_cu);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int HALO>
 static hipError_t launch_tile_halo(int kind, bool fuse_measure, int spt, int grid, size_t lds,
-                                   const SweepArgs &a, hipStream_t s)
+                                   const SweepArgs &a, hipStream_t s, int *per_cu)
 {
     if (kind == kMetro)
-        return fuse_measure ? launch_tile_spt<kMetro, true, HALO>(spt, grid, lds, a, s)
-                            : launch_tile_spt<kMetro, false, HALO>(spt, grid, lds, a, s);
+        return fuse_measure ? launch_tile_spt<kMetro, true, HALO>(spt, grid, lds, a, s, per_cu)
+                            : launch_tile_spt<kMetro, false, HALO>(spt, grid, lds, a, s, per_cu);
     if (kind == kOver)
-        return fuse_measure ? launch_tile_spt<kOver, true, HALO>(spt, grid, lds, a, s)
-                            : launch_tile_spt<kOver, false, HALO>(spt, grid, lds, a, s);
-    return launch_tile_spt<kMeas, false, HALO>(spt, grid, lds, a, s);
+        return fuse_measure ? launch_tile_spt<kOver, true, HALO>(spt, grid, lds, a, s, per_cu)
+                            : launch_tile_spt<kOver, false, HALO>(spt, grid, lds, a, s, per_cu);
+    return launch_tile_spt<kMeas, false, HALO>(spt, grid, lds, a, s, per_cu);
 }
 
 hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid, size_t lds,
-                           const SweepArgs &a, hipStream_t s)
+                           const SweepArgs &a, hipStream_t s, int *per_cu)
 {
-    if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, spt, grid, lds, a, s);
-    if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, spt, grid, lds, a, s);
+    if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, spt, grid, lds, a, s, per_cu);
+    if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, spt, grid, lds, a, s, per_cu);
     return hipErrorInvalidValue;
 }
 
 template <bool MEAS>
-static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s)
+static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
+                                 int *per_cu)
 {
     switch (spt) {
-    case 1: hipLaunchKernelGGL((k_or2_f32<MEAS, 1>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_or2_f32<MEAS, 2>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_or2_f32<MEAS, 3>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_or2_f32<MEAS, 4>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((k_or2_f32<MEAS, 5>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 6: hipLaunchKernelGGL((k_or2_f32<MEAS, 6>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_or2_f32<MEAS, 8>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 1: return launch_or_query(k_or2_f32<MEAS, 1>, grid, lds, a, s, per_cu);
+    case 2: return launch_or_query(k_or2_f32<MEAS, 2>, grid, lds, a, s, per_cu);
+    case 3: return launch_or_query(k_or2_f32<MEAS, 3>, grid, lds, a, s, per_cu);
+    case 4: return launch_or_query(k_or2_f32<MEAS, 4>, grid, lds, a, s, per_cu);
+    case 5: return launch_or_query(k_or2_f32<MEAS, 5>, grid, lds, a, s, per_cu);
+    case 6: return launch_or_query(k_or2_f32<MEAS, 6>, grid, lds, a, s, per_cu);
+    case 8: return launch_or_query(k_or2_f32<MEAS, 8>, grid, lds, a, s, per_cu);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds, const SweepArgs &a,
-                          hipStream_t s)
+                          hipStream_t s, int *per_cu)
 {
-    return fuse_measure ? launch_or2_spt<true>(spt, grid, lds, a, s) : launch_or2_spt<false>(spt, grid, lds, a, s);
+    return fuse_measure ? launch_or2_spt<true>(spt, grid, lds, a, s, per_cu)
+                        : launch_or2_spt<false>(spt, grid, lds, a, s, per_cu);
 }
 
 hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
