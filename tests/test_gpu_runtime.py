@@ -231,3 +231,21 @@ def test_fused_batch_with_mixed_tiles_equals_half_sweeps(gpu):
         b.sweep(1, 4)
         torch.cuda.synchronize()
         assert torch.equal(a.angles, b.angles), sweep
+
+
+def test_lattice_chain_does_not_depend_on_the_rest_of_the_batch(gpu):
+    """The counters carry the lattice index, so a lattice's chain is the same
+    alone and as the first lattice of a batch, exchange and fused launches
+    included (the other lattices only share the launches)."""
+    import torch
+    betas = [0.44, 0.45, 0.46]
+    alone = make([32], [betas], 41)
+    batch = make([32, 16, 24], [betas, [0.3, 0.5], [0.45]], 41)
+    obs_a = torch.zeros((4, 3, 5), dtype=torch.float64, device=gpu)
+    obs_b = torch.zeros((4, 6, 5), dtype=torch.float64, device=gpu)
+    alone.run(4, 1, 5, exchange_every=1, obs=obs_a)
+    batch.run(4, 1, 5, exchange_every=1, obs=obs_b)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(alone, 0), gpu_states(batch, 0))
+    assert alone.permutation()[:3] == batch.permutation()[:3]
+    assert np.allclose(obs_a.cpu().numpy(), obs_b[:, :3].cpu().numpy(), rtol=1e-12, atol=1e-9)
