@@ -156,3 +156,35 @@ def test_max_lattice_sampled(gpu):
     E1 = s.measure()[0, 0]
     assert abs(E1 - E0) <= 1e-7 * N
     s.close()
+
+
+def test_full_size_fp64_half_sweeps_match_oracle(gpu):
+    """The plain FP64 kernels (the single-replica reference the benchmark
+    reports) at L = 160, every site against the oracle, one half-sweep at a
+    time from the same state: Metropolis exactly (same decisions, same
+    proposals), over-relaxation within max(1e-12, 16 * 6 * 2^-53 / |h|) rad.
+    Whole sweeps are not compared at this size: over-relaxation amplifies
+    rounding differences between two correct FP64 evaluations roughly tenfold
+    per substep, so after ten substeps a few sites differ by ~1e-3 rad."""
+    L, beta, seed = L_BENCH, 0.4542, 4
+    s = make(L, [[beta]], seed, prec="fp64")
+    m0 = colour_mask(L, 0)
+    before = s.get_angles(0, 0)
+    s.sweep(1, 0)
+    after = s.get_angles(0, 0)
+    ref = before.copy()
+    acc0 = oracle.metro_half(ref, L, beta, seed, 0, 0, 0, 0, 0)
+    acc1 = oracle.metro_half(ref, L, beta, seed, 0, 0, 0, 0, 1)
+    assert np.max(circ(after, ref)) <= 1e-12
+    assert s.metro_accepts()[0] == acc0 + acc1
+    before = after
+    s.sweep(0, 1)
+    after = s.get_angles(0, 0)
+    for colour, base in ((0, before), (1, np.where(m0, after, before))):
+        ref = base.copy()
+        oracle.or_half(ref, L, colour)
+        hx, hy = field_numpy(base, L)
+        bound = np.maximum(1e-12, 16 * 6 * 2.0 ** -53 / np.maximum(np.hypot(hx, hy), 1e-300))
+        mask = m0 if colour == 0 else ~m0
+        assert np.all((circ(after, ref) <= bound)[mask]), colour
+    s.close()
