@@ -36,8 +36,11 @@
  *  - Randomness is Philox4x32-10 with key (seed mod 2^32, seed >> 32) and
  *    counter (c0, c1, (l << 16) | k, (phase << 24) | substep): c0 is the site
  *    (or exchange pair) index, c1 the sweep counter t (or exchange counter
- *    tau), phase 1 = initial state, 2 = Metropolis, 3 = exchange.  Uniforms
- *    are U(r) = (r >> 8) * 2^-24.  Random draws depend only on these
+ *    tau), phase 1 = initial state, 2 = Metropolis, 3 = exchange.  A
+ *    Metropolis block serves two sites of one colour, (x, y, 2m) and
+ *    (x xor 1, y, 2m+1): c0 is the even-plane site's index, which takes
+ *    words (r0, r1); the odd-plane site takes (r2, r3), written (a, b) below.
+ *    Uniforms are U(r) = (r >> 8) * 2^-24.  Random draws depend only on these
  *    counters, never on thread layout, so results do not depend on tiling.
  *  - All device work is ordered on the context's stream.  Calls return
  *    without waiting unless they hand data to host memory.
@@ -126,7 +129,7 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out);
 /*
  * One sweep of every configuration (Sec. II): n_metro Metropolis substeps,
  * each a half-sweep over colour 0 then colour 1 with proposal
- * theta' = 2*pi*U(r0) accepted iff U(r1) < exp(-beta*dE), then n_or
+ * theta' = 2*pi*U(a) accepted iff U(b) < exp(-beta*dE), then n_or
  * over-relaxation substeps (Eq. (2)), each colour 0 then colour 1.  Then
  * t <- t + 1.  n_metro, n_or >= 0 and n_metro + n_or >= 1.  Asynchronous.
  */
@@ -137,7 +140,10 @@ xy_status xy_sweep(xy_ctx ctx, int32_t n_metro, int32_t n_or);
  * index: obs[5*p + {0..4}] = {E, E/N, |m|, |m|^2, |m|^4} with
  * E = -sum_<ij> cos(theta_i - theta_j) (Eq. (1)) and
  * |m| = |sum_j (cos theta_j, sin theta_j)| / N (Eq. (4), one sample).
- * Sums are accumulated in float64.  obs has 5*R_total doubles; if
+ * The energy is summed as E = -sum_{i of colour 1} S_i . h_i, h_i the sum of
+ * the six neighbour spins (every bond has one end of each colour).  Terms
+ * are formed in the configuration's precision and accumulated in float64.
+ * obs has 5*R_total doubles; if
  * obs_on_device is nonzero it is a device pointer and the call is
  * asynchronous, otherwise it is host memory and the call waits for it.
  * Returns XY_ERR_STATE if any energy is not finite.
@@ -187,7 +193,9 @@ xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *m
  * I_y, I_z} with C_mu = sum_i cos(theta_i - theta_{i+mu}) and
  * I_mu = sum_i sin(theta_i - theta_{i+mu}), each bond (i, i+mu) once, in
  * float64.  Then rho_s = (1/3N) sum_mu [<C_mu> - beta <I_mu^2>].
- * Either ring may be NULL.  Asynchronous.
+ * Either ring may be NULL; with bonds_dev NULL the bond sums are not formed
+ * (the measurement then costs less).  E and -(C_x + C_y + C_z) agree to the
+ * rounding of the configuration's precision.  Asynchronous.
  */
 xy_status xy_run_ex(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
                     int32_t exchange_every, double *obs_dev, double *bonds_dev);
@@ -199,9 +207,9 @@ xy_status xy_run_ex(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
 xy_status xy_get_bond_sums(xy_ctx ctx, double *out, int32_t out_on_device);
 
 /*
- * Metropolis proposal: window = 0 (the default) proposes theta' = 2*pi*U(r0)
+ * Metropolis proposal: window = 0 (the default) proposes theta' = 2*pi*U(a)
  * uniformly on the circle; 0 < window <= 2*pi proposes the symmetric
- * restricted move theta' = theta + window*(U(r0) - 1/2), wrapped into
+ * restricted move theta' = theta + window*(U(a) - 1/2), wrapped into
  * [0, 2pi).  The paper does not state its proposal (Sec. II); the window
  * raises acceptance at large beta.  Applies to later sweeps.
  */

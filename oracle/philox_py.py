@@ -42,6 +42,19 @@ def counter(c0, c1, lat, pos, phase, substep):
             ((phase << 24) | substep) & MASK32)
 
 
+def metro_words(i, L, t, lat, pos, substep, key):
+    """The two words (proposal, acceptance) that site i = x + L (y + L z)
+    draws in a Metropolis substep: the same-colour sites (x, y, 2m) and
+    (x xor 1, y, 2m + 1) share the block whose first counter word is the
+    even-plane site's index; the even-plane site takes words 0, 1 and the
+    odd-plane site words 2, 3."""
+    x, y, z = i % L, (i // L) % L, i // (L * L)
+    i0 = (x ^ 1) + L * (y + L * (z - 1)) if z & 1 else i
+    r = philox4x32_10(counter(i0, t, lat, pos, PHASE_METRO, substep), key)
+    w = 2 * (z & 1)
+    return r[w], r[w + 1]
+
+
 def uniform(word):
     """U(r) = (r >> 8) * 2^-24, exactly representable in float32 and float64."""
     return (word >> 8) * (1.0 / 16777216.0)

@@ -120,13 +120,16 @@ void orc_init(double *theta, int L, int R, int lat, uint64_t seed)
  * Metropolis update of one site i, and the half-sweep over the sites of one
  * colour (Sec. II: checkerboard decomposition, all black sites, then all
  * white sites), which applies it to every site of that colour in increasing
- * i.  With
- * r = Philox(i, t, (lat << 16) | k, (METRO << 24) | substep):
- *     proposal   theta' = 2*pi*U(r0)        (uniform on the circle), or, with a
- *                window w > 0, theta' = wrap(theta + w (U(r0) - 1/2)) (symmetric)
+ * i.  Random words: the same-colour sites (x, y, 2m) and (x xor 1, y, 2m+1)
+ * share one Philox block
+ *     r = Philox(i0, t, (lat << 16) | k, (METRO << 24) | substep),
+ * i0 the natural index of the even-plane site; the even-plane site takes
+ * (a, b) = (r0, r1), the odd-plane site (a, b) = (r2, r3).  Then
+ *     proposal   theta' = 2*pi*U(a)         (uniform on the circle), or, with a
+ *                window w > 0, theta' = wrap(theta + w (U(a) - 1/2)) (symmetric)
  *     dE         = H(theta') - H(theta), evaluated from Eq. (1) over the six
  *                  bonds of site i:  sum_j [cos(theta - theta_j) - cos(theta' - theta_j)]
- *     accept iff U(r1) < exp(-beta * dE)
+ *     accept iff U(b) < exp(-beta * dE)
  * The site update returns 1 if accepted; the half-sweep returns the count.
  * ------------------------------------------------------------------------ */
 int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
@@ -135,12 +138,15 @@ int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t,
     int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
     int64_t nb[6];
     neighbours(L, x, y, z, nb);
+    int odd = z & 1;
+    int64_t i0 = odd ? (int64_t)(x ^ 1) + (int64_t)L * (y + (int64_t)L * (z - 1)) : i;
     uint32_t r[4];
-    draw(seed, (uint32_t)i, t, (uint32_t)lat, (uint32_t)k, ORC_PHASE_METRO, (uint32_t)substep, r);
+    draw(seed, (uint32_t)i0, t, (uint32_t)lat, (uint32_t)k, ORC_PHASE_METRO, (uint32_t)substep, r);
+    uint32_t wa = r[2 * odd], wb = r[2 * odd + 1];
     double th_old = theta[i];
-    double th_new = window > 0.0 ? wrap_angle(th_old + window * (orc_uniform(r[0]) - 0.5))
-                                 : TWO_PI * orc_uniform(r[0]);
-    double u = orc_uniform(r[1]);
+    double th_new = window > 0.0 ? wrap_angle(th_old + window * (orc_uniform(wa) - 0.5))
+                                 : TWO_PI * orc_uniform(wa);
+    double u = orc_uniform(wb);
     double dE = 0.0;
     for (int n = 0; n < 6; ++n) {
         double thj = theta[nb[n]];

@@ -210,7 +210,7 @@ int launch_grid(xy_ctx c, int items, bool fused, int kind, bool meas, int spt, s
     return resident > 0 ? std::min(items, resident) : items;
 }
 
-xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_measure)
+xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_measure, bool bonds = true)
 {
     SweepArgs a{};
     a.n_lat = c->n_lat;
@@ -223,6 +223,7 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
     a.colour = colour;
     a.substep = substep;
     a.recheck = (c->flags & XY_F_NO_RECHECK) ? 0 : 1;
+    a.bonds = bonds ? 1 : 0;
     a.window = c->window;
     a.window_t = (float)(c->window / 6.283185307179586476925286766559);
     a.partials = c->d_partials;
@@ -248,7 +249,7 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
 }
 
 // One fused over-relaxation substep from buffer `from` into buffer `to`.
-xy_status launch_or2(xy_ctx c, void *from, void *to, bool fuse_measure)
+xy_status launch_or2(xy_ctx c, void *from, void *to, bool fuse_measure, bool bonds = true)
 {
     SweepArgs a{};
     a.lats = c->d_lat_or2;
@@ -262,6 +263,7 @@ xy_status launch_or2(xy_ctx c, void *from, void *to, bool fuse_measure)
     a.k0 = c->k0;
     a.k1 = c->k1;
     a.partials = c->d_partials;
+    a.bonds = bonds ? 1 : 0;
     a.macc = c->d_macc;
     a.rq = c->d_rq;
     const int grid = launch_grid(c, a.total_items, true, 0, fuse_measure, c->spt2, c->lds2, a);
@@ -279,26 +281,27 @@ int fused_substeps(xy_ctx c, int n_or)
 }
 
 // Enqueue one sweep; if measure_last, the final kernel also produces the
-// measurement partials (in the item layout reported by partials_layout()).
-xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last)
+// measurement partials (in the item layout sweep_measures_fused() names),
+// with the bond sums of Eq. (6) when `bonds` is set.
+xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last, bool bonds = true)
 {
     const int n_fused = fused_substeps(c, n_or);
     const int total = 2 * (n_metro + n_or - n_fused) + n_fused;
     int h = 0;
     for (int s = 0; s < n_metro; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
-            xy_status st = launch_half(c, kMetro, col, s, measure_last && h == total - 1);
+            xy_status st = launch_half(c, kMetro, col, s, measure_last && h == total - 1, bonds);
             if (st) return st;
         }
     for (int s = 0; s < n_fused; ++s, ++h) {
         void *from = (s & 1) ? c->ang2 : c->ang;
         void *to = (s & 1) ? c->ang : c->ang2;
-        xy_status st = launch_or2(c, from, to, measure_last && h == total - 1);
+        xy_status st = launch_or2(c, from, to, measure_last && h == total - 1, bonds);
         if (st) return st;
     }
     for (int s = n_fused; s < n_or; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
-            xy_status st = launch_half(c, kOver, col, s, measure_last && h == total - 1);
+            xy_status st = launch_half(c, kOver, col, s, measure_last && h == total - 1, bonds);
             if (st) return st;
         }
     XY_HIP(c, launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream));
@@ -833,7 +836,7 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         hipStream_t user = c->stream;
         c->stream = c->cap_stream;
         XY_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        xy_status st = enqueue_sweep(c, n_metro, n_or, true);
+        xy_status st = enqueue_sweep(c, n_metro, n_or, true, bonds_dev != nullptr);
         if (!st)
             st = enqueue_finalize(c, sweep_measures_fused(c, n_or) ? kPartOr2 : kPartSweep, obs_dev, 1, true,
                                   exch != 0, bonds_dev);

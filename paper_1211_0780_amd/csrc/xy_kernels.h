@@ -7,9 +7,10 @@
 namespace xy {
 
 constexpr int kBlock = 256;  // threads per workgroup of the tiled and plain kernels
-// measurement partials per work item: Mx, My, C_x, C_y, C_z, I_x, I_y, I_z
-// (the energy is E = -(C_x + C_y + C_z), formed after the reduction)
-constexpr int kPartials = 8;
+// measurement partials per work item: S, Mx, My, C_x, C_y, C_z, I_x, I_y, I_z,
+// with S = sum over colour-1 sites of S_i . h_i, so that E = -S (Eq. (1));
+// the bond sums are filled only when asked for (SweepArgs::bonds)
+constexpr int kPartials = 9;
 
 // One lattice of a batch, as the kernels see it.  All offsets are in angle
 // elements (float for FP32, double for FP64).
@@ -67,6 +68,7 @@ struct SweepArgs {
     int32_t colour;
     int32_t substep;
     int32_t recheck;           // FP32 Metropolis: re-decide in float64 near the threshold
+    int32_t bonds;             // measuring: also form the bond sums C_mu, I_mu of Eq. (6)
     float window_t;            // Metropolis proposal window in turns (0: uniform proposal)
     double window;             // the same in radians, for the float64 kernels
     RecheckQueue *rq;          // where those decisions are queued

@@ -54,16 +54,20 @@ __device__ __forceinline__ void block_store_partials(const double (&v)[kPartials
     __syncthreads();
 }
 
-// Measurement terms of one colour-1 site i with unit vector (c, s), its six
-// colour-0 neighbours split by direction (+x, -x, +y, -y, +z, -z) and the
-// colour-0 partner site at the same storage index (pc, ps):
+// Measurement terms of one colour-1 site i with unit vector (c, s), the field
+// h = (hx, hy) of its six colour-0 neighbours (the sum every update kernel
+// forms, in the same order), those neighbours split by direction (+x, -x, +y,
+// -y, +z, -z) and the colour-0 partner site at the same storage index (pc, ps):
+//   S    += S_i . h_i
 //   M    += S_i + S_partner                (each site counted once)
+// and, when the bond sums of Eq. (6) are asked for,
 //   C_mu += S_i . (S_{i+mu} + S_{i-mu})     bonds (i, i+mu) and (i-mu, i)
 //   I_mu += sin(th_i - th_{i+mu}) - sin(th_i - th_{i-mu})
-// Every bond has exactly one colour-1 end, so the C_mu count each bond once
-// and the energy of Eq. (1) is E = -(C_x + C_y + C_z).  Each site's terms
-// are formed in the precision of its inputs (float32 on the float32 path: a
-// few 1e-7 relative, like the inputs themselves) and accumulated in float64.
+// Every bond has exactly one colour-1 end, so S counts each bond once and the
+// energy of Eq. (1) is E = -S (= -(C_x + C_y + C_z) up to rounding).  Each
+// site's terms are formed in the precision of its inputs (float32 on the
+// float32 path: a few 1e-7 relative, like the inputs themselves) and
+// accumulated in float64.
 // The fused multiply-adds are written out so that every kernel that inlines
 // this forms bit-identical terms (left to the compiler, contraction of the
 // products may differ between instantiations).
@@ -71,19 +75,22 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T>
-__device__ __forceinline__ void measure_site(double (&acc)[kPartials], T c, T s, T pc, T ps,
-                                             const T (&nc)[6], const T (&ns)[6])
+__device__ __forceinline__ void measure_site(double (&acc)[kPartials], bool bonds, T c, T s, T pc, T ps,
+                                             T hx, T hy, const T (&nc)[6], const T (&ns)[6])
 {
+    acc[0] += (double)fma_t(c, hx, s * hy);
+    acc[1] += (double)c + (double)pc;
+    acc[2] += (double)s + (double)ps;
+    if (bonds) {
 #pragma unroll
-    for (int mu = 0; mu < 3; ++mu) {
-        const T cp = nc[2 * mu], sp = ns[2 * mu];
-        const T cm = nc[2 * mu + 1], sm = ns[2 * mu + 1];
-        const T ssum = s * (sp + sm), cdif = c * (sp - sm);
-        acc[2 + mu] += (double)fma_t(c, cp + cm, ssum);
-        acc[5 + mu] += (double)fma_t(s, cp - cm, -cdif);
+        for (int mu = 0; mu < 3; ++mu) {
+            const T cp = nc[2 * mu], sp = ns[2 * mu];
+            const T cm = nc[2 * mu + 1], sm = ns[2 * mu + 1];
+            const T ssum = s * (sp + sm), cdif = c * (sp - sm);
+            acc[3 + mu] += (double)fma_t(c, cp + cm, ssum);
+            acc[6 + mu] += (double)fma_t(s, cp - cm, -cdif);
+        }
     }
-    acc[0] += (double)c + (double)pc;
-    acc[1] += (double)s + (double)ps;
 }
 
 __device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned long long *dst)
@@ -197,9 +204,10 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32
 // computed.
 //
 // KIND = kMetro / kOver updates colour a.colour; kMeas (colour 1) only
-// measures.  MEAS accumulates E = -sum_{i in colour 1} S_i . h_i (every
-// bond has exactly one colour-1 end) and M = sum over both colours into the
-// item's partials.  HALO = halo entries per thread (2*(L/2) <= HALO*kBlock).
+// measures.  MEAS accumulates S = sum_{i in colour 1} S_i . h_i (every
+// bond has exactly one colour-1 end, E = -S), M = sum over both colours and,
+// with a.bonds, the bond sums into the item's partials.  HALO = halo entries
+// per thread (2*(L/2) <= HALO*kBlock).
 // ---------------------------------------------------------------------------
 template <int KIND, bool MEAS, int SPT, int HALO>
 __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
@@ -304,6 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
         unsigned long long nacc = 0;
+        uint32_t kept0[SPT], kept1[SPT];  // Metropolis: words 2, 3 of the pair's Philox block
 
         // One plane.  pre_* were loaded one step ago and are consumed at the
         // end of this step; nxt_* are issued now and consumed next step.  The
@@ -352,10 +361,25 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 if constexpr (KIND == kOver) {
                     nv = overrelax_turns(cur[s], hx, hy);
                 } else if constexpr (KIND == kMetro) {
-                    const uint32_t p = (uint32_t)((ypar[s] + z) & 1);
-                    const uint32_t i = ibase[s] + p + LL * (uint32_t)z;
-                    const u32x4 r = philox4x32_10(i, t_sweep, c2, c3, a.k0, a.k1);
-                    const float u0 = unit24f(r.x), u1 = unit24f(r.y);
+                    // one Philox block per pair of planes (2m, 2m+1) of this
+                    // column: drawn at the even plane (or at the tile's first
+                    // plane when that is odd), its last two words kept for
+                    // the odd plane
+                    uint32_t w0, w1;
+                    if ((z & 1) == 0 || zz == 0) {
+                        const int zb = z & ~1;
+                        const uint32_t pb = (uint32_t)((ypar[s] + zb) & 1);
+                        const uint32_t ib = ibase[s] + pb + LL * (uint32_t)zb;
+                        const u32x4 r = philox4x32_10(ib, t_sweep, c2, c3, a.k0, a.k1);
+                        w0 = (z & 1) ? r.z : r.x;
+                        w1 = (z & 1) ? r.w : r.y;
+                        kept0[s] = r.z;
+                        kept1[s] = r.w;
+                    } else {
+                        w0 = kept0[s];
+                        w1 = kept1[s];
+                    }
+                    const float u0 = unit24f(w0), u1 = unit24f(w1);
                     // uniform proposal (exact in turns) or theta + w (u0 - 1/2)
                     const float prop = a.window_t > 0.0f
                                            ? frac_turn(__builtin_fmaf(a.window_t, u0 - 0.5f, cur[s]))
@@ -393,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const float nc[6] = {xp.c, xm.c, n2.c, n1.c, ocp[s].c, om.c};
                     const float ns[6] = {xp.s, xm.s, n2.s, n1.s, ocp[s].s, om.s};
                     // n3 is the other-colour site with the same storage index
-                    measure_site(acc, sc.c, sc.s, n3.c, n3.s, nc, ns);
+                    measure_site(acc, a.bonds != 0, sc.c, sc.s, n3.c, n3.s, hx, hy, nc, ns);
                 }
                 if constexpr (KIND != kMeas) bstore(nv, rown, voff[s], sz);
             }
@@ -641,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
                         const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0m2.c};
                         const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0m2.s};
                         // m3 is the colour-0 site with the same storage index
-                        measure_site(acc, sc.c, sc.s, m3.c, m3.s, nc, ns);
+                        measure_site(acc, a.bonds != 0, sc.c, sc.s, m3.c, m3.s, hx, hy, nc, ns);
                     }
                 }
             }
@@ -799,17 +823,22 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
                 nv = v;
             }
         } else if constexpr (KIND == kMetro) {
-            const uint32_t i = 2u * (uint32_t)j + (uint32_t)p +
-                               (uint32_t)L * ((uint32_t)y + (uint32_t)L * (uint32_t)z);
-            const u32x4 r = philox4x32_10(i, a.ctl->t, ((uint32_t)d.lat << 16) | (uint32_t)k,
+            // the Philox block of the plane pair (z - z mod 2, z - z mod 2 + 1):
+            // counter word 0 is the even-plane site of this column, whose x
+            // parity is the opposite of ours on an odd plane
+            const uint32_t zb = (uint32_t)(z & ~1);
+            const uint32_t pb = (uint32_t)p ^ (uint32_t)(z & 1);
+            const uint32_t ib = 2u * (uint32_t)j + pb + (uint32_t)L * ((uint32_t)y + (uint32_t)L * zb);
+            const u32x4 r = philox4x32_10(ib, a.ctl->t, ((uint32_t)d.lat << 16) | (uint32_t)k,
                                           (kPhaseMetro << 24) | (uint32_t)a.substep, a.k0, a.k1);
-            double prop = twopi * unit24d(r.x);
+            const uint32_t w0 = (z & 1) ? r.z : r.x, w1 = (z & 1) ? r.w : r.y;
+            double prop = twopi * unit24d(w0);
             if (a.window > 0.0) {
-                prop = fmod(th + a.window * (unit24d(r.x) - 0.5), twopi);
+                prop = fmod(th + a.window * (unit24d(w0) - 0.5), twopi);
                 if (prop < 0.0) prop += twopi;
                 if (prop >= twopi) prop = 0.0;
             }
-            const double u = unit24d(r.y);
+            const double u = unit24d(w1);
             double so, co, sp, cp;
             sincos(th, &so, &co);
             sincos(prop, &sp, &cp);
@@ -825,9 +854,10 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
             sincos(oth[q], &s0, &c0);
             // neighbour order (+x, -x, +y, -y, +z, -z); nb[0] (same j) is +x when p = 0
             const int64_t dir[6] = {p ? nb[1] : nb[0], p ? nb[0] : nb[1], nb[3], nb[2], nb[5], nb[4]};
-            double nc[6], ns[6];
-            for (int m = 0; m < 6; ++m) sincos(oth[dir[m]], &ns[m], &nc[m]);
-            measure_site(acc, c1, s1, c0, s0, nc, ns);
+            double nc[6] = {}, ns[6] = {};
+            if (a.bonds)
+                for (int m = 0; m < 6; ++m) sincos(oth[dir[m]], &ns[m], &nc[m]);
+            measure_site(acc, a.bonds != 0, c1, s1, c0, s0, hx, hy, nc, ns);
         }
         if constexpr (KIND != kMeas) own[q] = nv;
     }
@@ -904,7 +934,7 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
 #pragma unroll
             for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
             if (lane == 0) {
-                const double E = -(v[2] + v[3] + v[4]), mx = v[0], my = v[1];
+                const double E = -v[0], mx = v[1], my = v[2];
                 E_slot[pb + r] = E;
                 if (!isfinite(E) || !isfinite(mx) || !isfinite(my)) atomicOr(bad, 1);
                 const int kk = pos[pb + r];
@@ -921,7 +951,7 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
                 if (bout) {
                     double *o = bout + 6 * (int64_t)(pb + kk);
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) o[q] = v[2 + q];
+                    for (int q = 0; q < 6; ++q) o[q] = v[3 + q];
                 }
             }
         }

@@ -114,8 +114,8 @@ def test_full_size_metropolis_every_site(bench_sim):
     hx, hy = field_numpy(before, L)
     idx = np.flatnonzero(m0)[bad]
     for i in idx:
-        r = P.philox4x32_10(P.counter(int(i), t, 0, k, P.PHASE_METRO, 0), key)
-        prop, u = 2 * np.pi * P.uniform(r[0]), P.uniform(r[1])
+        a, b = P.metro_words(int(i), L, t, 0, k, 0, key)
+        prop, u = 2 * np.pi * P.uniform(a), P.uniform(b)
         dE = (np.cos(before[i]) - np.cos(prop)) * hx[i] + (np.sin(before[i]) - np.sin(prop)) * hy[i]
         assert abs(u - np.exp(-betas[k] * dE)) < 1e-6
     assert bad.size <= 5
@@ -148,7 +148,7 @@ def test_max_lattice_sampled(gpu):
     assert np.array_equal(got, want)
     s.sweep(1, 0)
     got = s.get_sites(sites)
-    want = np.array([2 * np.pi * P.uniform(P.philox4x32_10(P.counter(int(i), 0, 0, 0, P.PHASE_METRO, 0), key)[0])
+    want = np.array([2 * np.pi * P.uniform(P.metro_words(int(i), L, 0, 0, 0, 0, key)[0])
                      for i in sites])
     assert np.array_equal(got, want)
     E0 = s.measure()[0, 0]

@@ -51,7 +51,7 @@ def test_beta_zero_metropolis_is_closed_form(gpu, prec, L):
     s.sweep(1, 0)
     got = s.get_angles(0, 0)
     key = P.key_of(seed)
-    want = np.array([2 * np.pi * P.uniform(P.philox4x32_10(P.counter(i, 0, 0, 0, P.PHASE_METRO, 0), key)[0])
+    want = np.array([2 * np.pi * P.uniform(P.metro_words(i, L, 0, 0, 0, 0, key)[0])
                      for i in range(L ** 3)])
     assert np.array_equal(got, want)
     assert s.metro_accepts()[0] == L ** 3
@@ -67,9 +67,9 @@ def _metro_flip_ok(start, L, beta, seed, t, lat, k, sub, colour, got, ref):
     props = np.empty(idx.size)
     us = np.empty(idx.size)
     for n, i in enumerate(idx):
-        r = P.philox4x32_10(P.counter(int(i), t, lat, k, P.PHASE_METRO, sub), key)
-        props[n] = 2 * np.pi * P.uniform(r[0])
-        us[n] = P.uniform(r[1])
+        a, b = P.metro_words(int(i), L, t, lat, k, sub, key)
+        props[n] = 2 * np.pi * P.uniform(a)
+        us[n] = P.uniform(b)
     th = start[idx]
     dE = (np.cos(th) - np.cos(props)) * hx[idx] + (np.sin(th) - np.sin(props)) * hy[idx]
     p = np.exp(-beta * dE)
@@ -264,8 +264,10 @@ def test_bond_sums_match_oracle(gpu, prec):
     for k in range(3):
         ref = oracle.bond_sums(s.get_angles(0, k), L)
         assert np.allclose(got[k], ref, rtol=0, atol=tol * N), (got[k], ref)
+    # E is summed over colour-1 sites as -S_i . h_i: the same bonds, other rounding
     obs = s.measure()
-    assert np.allclose(obs[:, 0], -got[:, :3].sum(axis=1), rtol=1e-12, atol=1e-9)
+    etol = 1e-9 if prec == "fp64" else 2e-6
+    assert np.allclose(obs[:, 0], -got[:, :3].sum(axis=1), rtol=0, atol=etol * N)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -324,10 +326,10 @@ def test_windowed_metropolis_half_sweep(gpu, prec):
             bad = np.flatnonzero(d > tol)
             hx, hy = field_numpy(mid, L)
             for i in np.flatnonzero(m)[bad]:
-                r = P.philox4x32_10(P.counter(int(i), t, 0, k, P.PHASE_METRO, 0), key)
-                prop = (mid[i] + w * (P.uniform(r[0]) - 0.5)) % (2 * np.pi)
+                a, b = P.metro_words(int(i), L, t, 0, k, 0, key)
+                prop = (mid[i] + w * (P.uniform(a) - 0.5)) % (2 * np.pi)
                 dE = (np.cos(mid[i]) - np.cos(prop)) * hx[i] + (np.sin(mid[i]) - np.sin(prop)) * hy[i]
-                assert abs(P.uniform(r[1]) - np.exp(-beta * dE)) < 1e-6
+                assert abs(P.uniform(b) - np.exp(-beta * dE)) < 1e-6
             if prec == "fp64":
                 assert bad.size == 0
             mid[m] = after[k][m]

@@ -179,6 +179,29 @@ def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     assert np.array_equal(gpu_states(a), gpu_states(b))
 
 
+@pytest.mark.parametrize("prec,fused", [("fp32", True), ("fp32", False), ("fp64", False)])
+def test_measurement_without_bond_sums(gpu, prec, fused):
+    """A run that records no bond sums skips them in the measurement; the
+    chain, the observables and the exchanges stay those of a run that
+    records them."""
+    from paper_1211_0780_amd.sim import Sim
+    betas = list(np.linspace(0.44, 0.46, 4))
+    a = Sim([12, 10], [betas, betas[:3]], seed=8, prec=prec, fused_or=fused)
+    b = Sim([12, 10], [betas, betas[:3]], seed=8, prec=prec, fused_or=fused)
+    n = 4
+    oa = torch.zeros((n, 7, 5), dtype=torch.float64, device=gpu)
+    ob = torch.zeros((n, 7, 5), dtype=torch.float64, device=gpu)
+    bb = torch.zeros((n, 7, 6), dtype=torch.float64, device=gpu)
+    a.run(n, 1, 4, exchange_every=1, obs=oa)
+    b.run(n, 1, 4, exchange_every=1, obs=ob, bonds=bb)
+    torch.cuda.synchronize()
+    for l in range(2):
+        assert np.array_equal(gpu_states(a, l), gpu_states(b, l))
+        assert a.permutation(l) == b.permutation(l)
+    assert np.array_equal(oa.cpu().numpy(), ob.cpu().numpy())
+    assert np.all(bb.cpu().numpy()[:, :, :3] != 0.0)
+
+
 def test_fused_measurement_equals_half_sweep_measurement(gpu):
     from paper_1211_0780_amd.sim import Sim
     betas = list(np.linspace(0.44, 0.46, 4))

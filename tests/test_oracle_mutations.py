@@ -38,6 +38,10 @@ MUTATIONS = {
     "philox_key_bump": ("k1 += W1;", "k1 += W0;"),
     "uniform_shift": ("return (double)(r >> 8) * (1.0 / 16777216.0);",
                       "return (double)(r >> 9) * (1.0 / 16777216.0);"),
+    "metro_odd_plane_takes_words_0_1": ("uint32_t wa = r[2 * odd], wb = r[2 * odd + 1];",
+                                        "uint32_t wa = r[0], wb = r[1];"),
+    "metro_pair_partner_keeps_x": ("int64_t i0 = odd ? (int64_t)(x ^ 1) + ",
+                                   "int64_t i0 = odd ? (int64_t)x + "),
     "init_uses_word_1": ("theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[0]);",
                          "theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[1]);"),
 }

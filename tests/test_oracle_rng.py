@@ -103,3 +103,24 @@ def test_init_is_two_pi_uniform(orc):
             r = P.philox4x32_10(P.counter(i, 0, lat, k, P.PHASE_INIT, 0), key)
             assert th[k, i] == 2 * np.pi * P.uniform(r[0])
     assert th.min() >= 0.0 and th.max() < 2 * np.pi
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_metropolis_words_are_distinct_and_paired(L):
+    """Every site of a substep reads its own pair of words, and a block serves
+    exactly two sites of one colour on planes 2m and 2m + 1: the even-plane
+    site (whose index is the block's counter word) and its x-neighbour's
+    same-colour partner one plane up."""
+    key = P.key_of(5)
+    seen, blocks = {}, {}
+    for i in range(L ** 3):
+        x, y, z = i % L, (i // L) % L, i // (L * L)
+        words = P.metro_words(i, L, 3, 0, 1, 0, key)
+        assert words not in seen, (i, seen.get(words))
+        seen[words] = i
+        i0 = (x ^ 1) + L * (y + L * (z - 1)) if z & 1 else i
+        full = P.philox4x32_10(P.counter(i0, 3, 0, 1, P.PHASE_METRO, 0), key)
+        assert words == tuple(full[2 * (z & 1): 2 * (z & 1) + 2])
+        blocks.setdefault(i0, []).append((x + y + z) & 1)
+    assert len(blocks) == L ** 3 // 2
+    assert all(len(c) == 2 and c[0] == c[1] for c in blocks.values())

@@ -46,8 +46,8 @@ def test_beta_zero_metropolis_accepts_every_proposal(orc):
         acc = orc.metro_half(th, L, 0.0, seed, t, lat, k, s, c)
         assert acc == L ** 3 // 2
     for i in range(L ** 3):
-        r = P.philox4x32_10(P.counter(i, t, lat, k, P.PHASE_METRO, s), key)
-        assert th[i] == 2 * np.pi * P.uniform(r[0])
+        a, _ = P.metro_words(i, L, t, lat, k, s, key)
+        assert th[i] == 2 * np.pi * P.uniform(a)
 
 
 def test_metropolis_only_touches_its_colour(orc):
@@ -74,9 +74,9 @@ def test_metropolis_decisions_follow_local_energy(orc):
         key = P.key_of(seed)
         n_checked = 0
         for i in np.flatnonzero(colour_mask(L, c).ravel()):
-            r = P.philox4x32_10(P.counter(int(i), t, lat, k, P.PHASE_METRO, s), key)
-            prop = 2 * np.pi * P.uniform(r[0])
-            u = P.uniform(r[1])
+            a, b = P.metro_words(int(i), L, t, lat, k, s, key)
+            prop = 2 * np.pi * P.uniform(a)
+            u = P.uniform(b)
             dE = (np.cos(th0[i]) - np.cos(prop)) * hx[i] + (np.sin(th0[i]) - np.sin(prop)) * hy[i]
             p = np.exp(-beta * dE)
             if abs(u - p) < 1e-12:
@@ -236,9 +236,9 @@ def test_windowed_metropolis_proposal_and_decisions(orc):
     key = P.key_of(seed)
     moved = 0
     for i in np.flatnonzero(colour_mask(L, 0).ravel()):
-        r = P.philox4x32_10(P.counter(int(i), t, lat, k, P.PHASE_METRO, s), key)
-        prop = (th0[i] + w * (P.uniform(r[0]) - 0.5)) % (2 * np.pi)
-        u = P.uniform(r[1])
+        a, b = P.metro_words(int(i), L, t, lat, k, s, key)
+        prop = (th0[i] + w * (P.uniform(a) - 0.5)) % (2 * np.pi)
+        u = P.uniform(b)
         dE = (np.cos(th0[i]) - np.cos(prop)) * hx[i] + (np.sin(th0[i]) - np.sin(prop)) * hy[i]
         p = np.exp(-beta * dE)
         if abs(u - p) < 1e-12:
