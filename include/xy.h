@@ -164,7 +164,8 @@ xy_status xy_measure(xy_ctx ctx, double *obs, int32_t obs_on_device);
 xy_status xy_exchange(xy_ctx ctx, int64_t *n_acc);
 
 /*
- * The production loop, captured once as a HIP graph and replayed: n_sweeps
+ * The production loop, captured as HIP graphs (several sweeps per graph when
+ * exchange_every is 0 or 1) and replayed: n_sweeps
  * times { xy_sweep(n_metro, n_or); measure into obs_dev; exchange if
  * (sweep index + 1) % exchange_every == 0 }.  exchange_every = 0 disables
  * exchange.  obs_dev: device buffer of n_sweeps*5*R_total doubles, sweep s at
@@ -178,7 +179,7 @@ xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
  * xy_sweep with each group of consecutive launches of one kind bracketed by
  * HIP events on the context's stream (profiling aid; same result as
  * xy_sweep).  ms[0..3] receive the device time of the Metropolis half-sweeps
- * (with their float64 re-decision kernels), the over-relaxation
+ * (their float64 re-decision included), the over-relaxation
  * half-sweeps, the fused over-relaxation substeps (one launch updates both
  * colours) and the counter update; launches[0..3] the number of half-sweep,
  * half-sweep, fused and counter launches in each group.  Waits.

@@ -35,14 +35,19 @@ struct Tiling {
 };
 
 struct GraphKey {
-    int n_metro = -1, n_or = -1, exch = -1;
+    int n_metro = -1, n_or = -1, exch = -1, batch = 0;
     double *obs = nullptr, *bonds = nullptr;
     bool operator==(const GraphKey &o) const
     {
-        return n_metro == o.n_metro && n_or == o.n_or && exch == o.exch && obs == o.obs &&
-               bonds == o.bonds;
+        return n_metro == o.n_metro && n_or == o.n_or && exch == o.exch && batch == o.batch &&
+               obs == o.obs && bonds == o.bonds;
     }
 };
+
+// Sweeps captured in one graph when every sweep of a loop is the same
+// (exchange after every sweep or never): fewer graph launches, and the gap
+// between consecutive graphs is paid once per batch.
+constexpr int kSweepsPerGraph = 8;
 
 struct GraphEntry {
     GraphKey key;
@@ -236,9 +241,7 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
         a.total_items = meas_item_space ? c->items_meas : c->items_sweep;
         const int grid = launch_grid(c, a.total_items, false, kind, fuse_measure, c->spt, c->lds_bytes, a);
         e = launch_tile_f32(kind, fuse_measure, c->spt, c->halo, grid, c->lds_bytes, a, c->stream);
-        if (e == hipSuccess && kind == kMetro && a.recheck)
-            e = launch_recheck(c->d_lat_sweep, c->ang, c->d_beta, c->d_pos, colour, c->d_rq, c->d_macc,
-                               c->stream);
+        if (e == hipSuccess && kind == kMetro && a.recheck) e = launch_recheck(a, c->stream);
     } else {
         a.lats = c->d_lat_sweep;
         a.total_items = c->items_sweep;
@@ -280,47 +283,65 @@ int fused_substeps(xy_ctx c, int n_or)
     return c->fused_or ? n_or - (n_or & 1) : 0;
 }
 
-// Enqueue one sweep; if measure_last, the final kernel also produces the
-// measurement partials (in the item layout sweep_measures_fused() names),
-// with the bond sums of Eq. (6) when `bonds` is set.
-xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last, bool bonds = true)
+enum PartialsLayout { kPartMeas = 0, kPartSweep = 1, kPartOr2 = 2 };
+
+// A sweep that ends on a float32 Metropolis half-sweep with float64
+// re-decision is measured by a separate pass after it: the re-decision may
+// still change sites that the half-sweep has already measured.
+bool measures_after_sweep(xy_ctx c, int n_or)
+{
+    return n_or == 0 && c->prec == XY_FP32 && !(c->flags & XY_F_NO_RECHECK);
+}
+
+// Which item layout the measurement partials of a sweep come from.
+int sweep_partials_layout(xy_ctx c, int n_or)
+{
+    const int n_fused = fused_substeps(c, n_or);
+    if (n_fused > 0 && n_fused == n_or) return kPartOr2;
+    return measures_after_sweep(c, n_or) ? kPartMeas : kPartSweep;
+}
+
+// Enqueue one sweep; if measure_last, the sweep also produces the
+// measurement partials of its final configuration (in the item layout
+// sweep_partials_layout() names), with the bond sums of Eq. (6) when
+// `bonds` is set.  Without `tick` the caller advances the sweep counter
+// itself (after the sweep's last kernel).
+xy_status enqueue_sweep(xy_ctx c, int n_metro, int n_or, bool measure_last, bool bonds = true,
+                        bool tick = true)
 {
     const int n_fused = fused_substeps(c, n_or);
     const int total = 2 * (n_metro + n_or - n_fused) + n_fused;
+    const bool meas_after = measure_last && measures_after_sweep(c, n_or);
+    const bool meas_fused = measure_last && !meas_after;
     int h = 0;
     for (int s = 0; s < n_metro; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
-            xy_status st = launch_half(c, kMetro, col, s, measure_last && h == total - 1, bonds);
+            xy_status st = launch_half(c, kMetro, col, s, meas_fused && h == total - 1, bonds);
             if (st) return st;
         }
     for (int s = 0; s < n_fused; ++s, ++h) {
         void *from = (s & 1) ? c->ang2 : c->ang;
         void *to = (s & 1) ? c->ang : c->ang2;
-        xy_status st = launch_or2(c, from, to, measure_last && h == total - 1, bonds);
+        xy_status st = launch_or2(c, from, to, meas_fused && h == total - 1, bonds);
         if (st) return st;
     }
     for (int s = n_fused; s < n_or; ++s)
         for (int col = 0; col < 2; ++col, ++h) {
-            xy_status st = launch_half(c, kOver, col, s, measure_last && h == total - 1, bonds);
+            xy_status st = launch_half(c, kOver, col, s, meas_fused && h == total - 1, bonds);
             if (st) return st;
         }
-    XY_HIP(c, launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream));
+    if (meas_after) {
+        xy_status st = launch_half(c, kMeas, 1, 0, false, bonds);
+        if (st) return st;
+    }
+    if (tick) XY_HIP(c, launch_tick(c->d_ctl, 1u, 0u, 0u, 0, c->stream));
     return XY_OK;
-}
-
-// Which item layout the measurement partials of a sweep come from.
-bool sweep_measures_fused(xy_ctx c, int n_or)
-{
-    const int n_fused = fused_substeps(c, n_or);
-    return n_fused > 0 && n_fused == n_or;
 }
 
 xy_status enqueue_measure_kernel(xy_ctx c)
 {
     return launch_half(c, kMeas, 1, 0, false);
 }
-
-enum PartialsLayout { kPartMeas = 0, kPartSweep = 1, kPartOr2 = 2 };
 
 const LatDev *meas_layout_dev(xy_ctx c, int layout)
 {
@@ -823,9 +844,11 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         return fail(c, XY_ERR_STATE, "counters would overflow 32 bits");
     if (n_sweeps == 0) return XY_OK;
 
-    // Two captured graphs: sweep + measure, and sweep + measure + exchange.
-    auto get_graph = [&](int exch, hipGraphExec_t *exec) -> xy_status {
-        GraphKey key{n_metro, n_or, exch, obs_dev, bonds_dev};
+    // Captured graphs of `batch` sweeps, each sweep + measure (+ exchange),
+    // then one counter update (t, tau, observable ring).  Nothing in the
+    // measurement or the exchange reads t, so it advances with the others.
+    auto get_graph = [&](int exch, int batch, hipGraphExec_t *exec) -> xy_status {
+        GraphKey key{n_metro, n_or, exch, batch, obs_dev, bonds_dev};
         for (auto &g : c->graphs)
             if (g.key == key) {
                 *exec = g.exec;
@@ -836,14 +859,17 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         hipStream_t user = c->stream;
         c->stream = c->cap_stream;
         XY_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        xy_status st = enqueue_sweep(c, n_metro, n_or, true, bonds_dev != nullptr);
-        if (!st)
-            st = enqueue_finalize(c, sweep_measures_fused(c, n_or) ? kPartOr2 : kPartSweep, obs_dev, 1, true,
-                                  exch != 0, bonds_dev);
-        if (!st) {
-            hipError_t e = launch_tick(c->d_ctl, 0u, exch ? 1u : 0u, (obs_dev || bonds_dev) ? 1u : 0u, 0,
-                                       c->cap_stream);
-            if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
+        xy_status st = XY_OK;
+        for (int b = 0; b < batch && !st; ++b) {
+            st = enqueue_sweep(c, n_metro, n_or, true, bonds_dev != nullptr, false);
+            if (!st)
+                st = enqueue_finalize(c, sweep_partials_layout(c, n_or), obs_dev, 1, true, exch != 0,
+                                      bonds_dev);
+            if (!st) {
+                hipError_t e = launch_tick(c->d_ctl, 1u, exch ? 1u : 0u, (obs_dev || bonds_dev) ? 1u : 0u, 0,
+                                           c->cap_stream);
+                if (e != hipSuccess) st = fail(c, XY_ERR_HIP, "tick launch failed");
+            }
         }
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
@@ -864,16 +890,31 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         return XY_OK;
     };
 
-    hipGraphExec_t g_plain = nullptr, g_exch = nullptr;
     xy_status st;
-    if ((st = get_graph(0, &g_plain))) return st;
-    if (exchange_every > 0 && (st = get_graph(1, &g_exch))) return st;
-    XY_HIP(c, launch_tick(c->d_ctl, 0u, 0u, 0u, 1, c->stream));  // ring <- 0
-    for (int s = 0; s < n_sweeps; ++s) {
-        const bool ex = exchange_every > 0 && ((s + 1) % exchange_every) == 0;
-        XY_HIP(c, hipGraphLaunch(ex ? g_exch : g_plain, c->stream));
-        c->t += 1;
-        if (ex) c->tau += 1;
+    if (exchange_every <= 1) {
+        // every sweep alike: batches of kSweepsPerGraph, then single sweeps
+        const int ex = exchange_every;
+        const int batch = std::min(n_sweeps, kSweepsPerGraph);
+        const int n_batches = n_sweeps / batch, rest = n_sweeps - n_batches * batch;
+        hipGraphExec_t g_batch = nullptr, g_one = nullptr;
+        if ((st = get_graph(ex, batch, &g_batch))) return st;
+        if (rest > 0 && (st = get_graph(ex, 1, &g_one))) return st;
+        XY_HIP(c, launch_tick(c->d_ctl, 0u, 0u, 0u, 1, c->stream));  // ring <- 0
+        for (int b = 0; b < n_batches; ++b) XY_HIP(c, hipGraphLaunch(g_batch, c->stream));
+        for (int s = 0; s < rest; ++s) XY_HIP(c, hipGraphLaunch(g_one, c->stream));
+        c->t += (uint64_t)n_sweeps;
+        if (ex) c->tau += (uint64_t)n_sweeps;
+    } else {
+        hipGraphExec_t g_plain = nullptr, g_exch = nullptr;
+        if ((st = get_graph(0, 1, &g_plain))) return st;
+        if ((st = get_graph(1, 1, &g_exch))) return st;
+        XY_HIP(c, launch_tick(c->d_ctl, 0u, 0u, 0u, 1, c->stream));  // ring <- 0
+        for (int s = 0; s < n_sweeps; ++s) {
+            const bool ex = ((s + 1) % exchange_every) == 0;
+            XY_HIP(c, hipGraphLaunch(ex ? g_exch : g_plain, c->stream));
+            c->t += 1;
+            if (ex) c->tau += 1;
+        }
     }
     c->e_fresh = true;
     c->bonds_fresh = false;

@@ -83,8 +83,7 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int g
                            size_t lds_bytes, const SweepArgs &a, hipStream_t s, int *per_cu = nullptr);
 hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
                           hipStream_t s, int *per_cu = nullptr);
-hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
-                          int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s);
+hipError_t launch_recheck(const SweepArgs &a, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);
 hipError_t launch_init(bool fp32, bool ordered, const LatDev *lats, int n_lat,
                        int64_t total_sites, void *ang, uint32_t k0, uint32_t k1,

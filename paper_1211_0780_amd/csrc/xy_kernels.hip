@@ -192,6 +192,71 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Re-take one queued near-threshold Metropolis decision in float64: the six
+// neighbour angles (other colour, untouched by this half-sweep) are read
+// again, dE and exp(-beta dE) evaluated in double, and the site is corrected
+// where the float64 decision differs.
+// ---------------------------------------------------------------------------
+__device__ void recheck_entry(const SweepArgs &a, const RecheckEntry &en)
+{
+    const double twopi = 6.283185307179586476925286766559;
+    const LatDev d = a.lats[en.li];
+    const int L = d.L, half = d.half;
+    const int64_t plane = (int64_t)L * half;
+    const int z = (int)(en.q / plane);
+    const int rem = (int)(en.q - (int64_t)z * plane);
+    const int y = rem / half, j = rem - y * half;
+    const int p = (a.colour + y + z) & 1;
+    float *angs = (float *)a.ang + d.base + (int64_t)en.slot * d.N;
+    float *own = angs + (int64_t)a.colour * (d.N / 2);
+    const float *oth = angs + (int64_t)(a.colour ^ 1) * (d.N / 2);
+    const int ym = (y == 0) ? L - 1 : y - 1, yp = (y + 1 == L) ? 0 : y + 1;
+    const int zm = (z == 0) ? L - 1 : z - 1, zp = (z + 1 == L) ? 0 : z + 1;
+    const int jx = p ? ((j + 1 == half) ? 0 : j + 1) : ((j == 0) ? half - 1 : j - 1);
+    const int64_t zo = (int64_t)z * plane;
+    const int64_t nb[6] = {zo + (int64_t)y * half + j,  zo + (int64_t)y * half + jx,
+                           zo + (int64_t)ym * half + j, zo + (int64_t)yp * half + j,
+                           (int64_t)zm * plane + (int64_t)y * half + j,
+                           (int64_t)zp * plane + (int64_t)y * half + j};
+    double hx = 0.0, hy = 0.0;
+    for (int m = 0; m < 6; ++m) {
+        double sn, cn;
+        sincos((double)oth[nb[m]] * twopi, &sn, &cn);
+        hx += cn;
+        hy += sn;
+    }
+    double so, co, sp, cp;
+    sincos((double)en.cur * twopi, &so, &co);
+    sincos((double)en.prop * twopi, &sp, &cp);
+    const double dE = (co - cp) * hx + (so - sp) * hy;
+    const int k = a.pos[d.pos_base + en.slot];
+    const bool acc = (double)en.u1 < exp(-a.beta[d.pos_base + k] * dE);
+    if ((int)acc != en.fp32_accept) {
+        own[en.q] = acc ? en.prop : en.cur;
+        atomicAdd(a.macc + d.pos_base + k, acc ? 1ull : ~0ull);  // +1 or -1
+    }
+}
+
+// The queued decisions of one half-sweep, re-taken by a follow-up launch (the
+// kernel boundary orders it after every workgroup of the half-sweep).  The
+// last workgroup to finish empties the queue for the next half-sweep.
+__global__ __launch_bounds__(kBlock) void k_recheck(SweepArgs a)
+{
+    const uint32_t n = min(a.rq->count, a.rq->capacity);
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
+        recheck_entry(a, a.rq->entries[e]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.rq->done, 1u) == gridDim.x - 1) {
+            a.rq->count = 0;
+            a.rq->done = 0;
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Tiled FP32 half-sweep.  A work item is (lattice, slot, y-tile, z-chunk):
 // TY rows of L/2 sites of the updated colour, streamed over TZ planes.  Each
 // thread owns SPT (y, j) columns of the tile.  The other colour is read once
@@ -701,69 +766,6 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Re-take the queued near-threshold Metropolis decisions in float64: the six
-// neighbour angles (other colour, untouched by this half-sweep) are read
-// again, dE and exp(-beta dE) evaluated in double, and the site is corrected
-// where the float64 decision differs.  The last workgroup to finish empties
-// the queue for the next half-sweep.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_recheck(const LatDev *lats, float *ang,
-                                                    const double *beta, const int32_t *pos,
-                                                    int colour, RecheckQueue *rq,
-                                                    unsigned long long *macc)
-{
-    const double twopi = 6.283185307179586476925286766559;
-    const uint32_t n = min(rq->count, rq->capacity);
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const RecheckEntry en = rq->entries[e];
-        const LatDev d = lats[en.li];
-        const int L = d.L, half = d.half;
-        const int64_t plane = (int64_t)L * half;
-        const int z = (int)(en.q / plane);
-        const int rem = (int)(en.q - (int64_t)z * plane);
-        const int y = rem / half, j = rem - y * half;
-        const int p = (colour + y + z) & 1;
-        float *angs = ang + d.base + (int64_t)en.slot * d.N;
-        float *own = angs + (int64_t)colour * (d.N / 2);
-        const float *oth = angs + (int64_t)(colour ^ 1) * (d.N / 2);
-        const int ym = (y == 0) ? L - 1 : y - 1, yp = (y + 1 == L) ? 0 : y + 1;
-        const int zm = (z == 0) ? L - 1 : z - 1, zp = (z + 1 == L) ? 0 : z + 1;
-        const int jx = p ? ((j + 1 == half) ? 0 : j + 1) : ((j == 0) ? half - 1 : j - 1);
-        const int64_t zo = (int64_t)z * plane;
-        const int64_t nb[6] = {zo + (int64_t)y * half + j,  zo + (int64_t)y * half + jx,
-                               zo + (int64_t)ym * half + j, zo + (int64_t)yp * half + j,
-                               (int64_t)zm * plane + (int64_t)y * half + j,
-                               (int64_t)zp * plane + (int64_t)y * half + j};
-        double hx = 0.0, hy = 0.0;
-        for (int m = 0; m < 6; ++m) {
-            double sn, cn;
-            sincos((double)oth[nb[m]] * twopi, &sn, &cn);
-            hx += cn;
-            hy += sn;
-        }
-        double so, co, sp, cp;
-        sincos((double)en.cur * twopi, &so, &co);
-        sincos((double)en.prop * twopi, &sp, &cp);
-        const double dE = (co - cp) * hx + (so - sp) * hy;
-        const int k = pos[d.pos_base + en.slot];
-        const bool acc = (double)en.u1 < exp(-beta[d.pos_base + k] * dE);
-        if ((int)acc != en.fp32_accept) {
-            own[en.q] = acc ? en.prop : en.cur;
-            atomicAdd(macc + d.pos_base + k, acc ? 1ull : ~0ull);  // +1 or -1
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&rq->done, 1u) == gridDim.x - 1) {
-            rq->count = 0;
-            rq->done = 0;
-            __threadfence();
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Plain FP64 half-sweep: one thread per site of the updated colour, all six
 // neighbours read straight from global memory, every transcendental in
 // double.  A work item is (lattice, slot, block of kBlock sites).
@@ -1077,11 +1079,9 @@ hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds, cons
                         : launch_or2_spt<false>(spt, grid, lds, a, s, per_cu);
 }
 
-hipError_t launch_recheck(const LatDev *lats, void *ang, const double *beta, const int32_t *pos,
-                          int colour, RecheckQueue *rq, unsigned long long *macc, hipStream_t s)
+hipError_t launch_recheck(const SweepArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_recheck, dim3(16), dim3(kBlock), 0, s, lats, (float *)ang, beta, pos, colour,
-                       rq, macc);
+    hipLaunchKernelGGL(k_recheck, dim3(16), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

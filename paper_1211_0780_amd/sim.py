@@ -113,7 +113,7 @@ class Sim:
     def sweep_profiled(self, n_metro=1, n_or=1):
         """xy_sweep with HIP events around each group of consecutive launches of
         one kind: returns the group's milliseconds and its launch count, keyed
-        'metro' (half-sweeps with their re-decision kernels), 'over'
+        'metro' (half-sweeps, float64 re-decision included), 'over'
         (half-sweeps), 'over_fused' (fused substeps) and 'other'."""
         ms = (ctypes.c_double * 4)()
         n = (ctypes.c_int32 * 4)()

@@ -202,6 +202,49 @@ def test_measurement_without_bond_sums(gpu, prec, fused):
     assert np.all(bb.cpu().numpy()[:, :, :3] != 0.0)
 
 
+@pytest.mark.parametrize("exchange_every", [0, 1])
+def test_batched_graph_replay_matches_single_sweeps(gpu, exchange_every):
+    """A long run replays graphs of several sweeps plus single-sweep graphs
+    for the remainder; its chain, permutation, counters and observable ring
+    equal those of one-sweep runs."""
+    betas = list(np.linspace(0.44, 0.46, 4))
+    n = 11
+    a = make(10, betas, 21)
+    b = make(10, betas, 21)
+    oa = torch.zeros((n, 4, 5), dtype=torch.float64, device=gpu)
+    ob = torch.zeros((n, 4, 5), dtype=torch.float64, device=gpu)
+    a.run(n, 1, 2, exchange_every=exchange_every, obs=oa)
+    for s in range(n):
+        b.run(1, 1, 2, exchange_every=exchange_every, obs=ob[s:s + 1])
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.permutation() == b.permutation()
+    assert a.counters() == b.counters() == (n, n * exchange_every)
+    assert np.array_equal(oa.cpu().numpy(), ob.cpu().numpy())
+
+
+def test_metropolis_only_sweeps_measure_the_final_state(gpu):
+    """With no over-relaxation the sweep ends on a Metropolis half-sweep whose
+    near-threshold decisions are re-taken after it; the loop then measures
+    the final configuration with the standalone pass, exactly as an eager
+    sweep + measure + exchange does."""
+    betas = list(np.linspace(0.44, 0.46, 4))
+    n = 5
+    a = make(12, betas, 17)
+    b = make(12, betas, 17)
+    oa = torch.zeros((n, 4, 5), dtype=torch.float64, device=gpu)
+    a.run(n, 1, 0, exchange_every=1, obs=oa)
+    torch.cuda.synchronize()
+    ob = []
+    for _ in range(n):
+        b.sweep(1, 0)
+        ob.append(b.measure())
+        b.exchange()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.permutation() == b.permutation()
+    assert np.array_equal(oa.cpu().numpy(), np.stack(ob))
+
+
 def test_fused_measurement_equals_half_sweep_measurement(gpu):
     from paper_1211_0780_amd.sim import Sim
     betas = list(np.linspace(0.44, 0.46, 4))
