@@ -45,7 +45,7 @@ def test_random_start_batch_uses_lattice_index(gpu):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("L", [4, 8, 12])
 def test_beta_zero_metropolis_is_closed_form(gpu, prec, L):
-    """beta = 0: every proposal is accepted, theta = 2 pi U(r0) exactly."""
+    """beta = 0: every proposal is accepted, theta = 2 pi U(a) exactly (a = the site's proposal word)."""
     seed = 77
     s = make(L, [0.0], seed, prec)
     s.sweep(1, 0)

@@ -38,7 +38,7 @@ def circ(a, b):
 
 
 def test_beta_zero_metropolis_accepts_every_proposal(orc):
-    """At beta = 0, exp(-beta dE) = 1 > u, so every site takes theta' = 2 pi U(r0)."""
+    """At beta = 0, exp(-beta dE) = 1 > u, so every site takes theta' = 2 pi U(a), a its proposal word."""
     L, seed, t, lat, k, s = 6, 77, 5, 1, 3, 2
     th = orc.init(L, 1, seed, lat)[0].copy()
     key = P.key_of(seed)
@@ -226,7 +226,7 @@ def test_exchange_acceptance_rate(orc):
 
 
 def test_windowed_metropolis_proposal_and_decisions(orc):
-    """Window w: proposal wrap(theta + w (U(r0) - 1/2)), decided by u < exp(-beta dE)."""
+    """Window w: proposal wrap(theta + w (U(a) - 1/2)), decided by u < exp(-beta dE)."""
     L, seed, t, lat, k, s, beta, w = 6, 12, 4, 0, 1, 0, 0.6, 1.3
     th0 = orc.init(L, 1, seed)[0].copy()
     th = th0.copy()
