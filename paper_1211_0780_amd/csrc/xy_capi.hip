@@ -203,7 +203,8 @@ int launch_grid(xy_ctx c, int items, bool fused, int kind, bool meas, int spt, s
 {
     if (c->grid_sweep > 0) return std::min(items, c->grid_sweep);
     const uint64_t key = ((uint64_t)lds << 32) | ((uint64_t)fused << 24) | ((uint64_t)c->halo << 16) |
-                         ((uint64_t)spt << 8) | ((uint64_t)meas << 4) | (uint64_t)kind;
+                         ((uint64_t)spt << 8) | ((uint64_t)(a.bonds != 0) << 5) | ((uint64_t)meas << 4) |
+                         (uint64_t)kind;
     auto it = c->per_cu.find(key);
     if (it == c->per_cu.end()) {
         int n = 0;
