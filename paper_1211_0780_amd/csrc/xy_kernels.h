@@ -11,6 +11,7 @@ constexpr int kBlock = 256;  // threads per workgroup of the tiled and plain ker
 // with S = sum over colour-1 sites of S_i . h_i, so that E = -S (Eq. (1));
 // the bond sums are filled only when asked for (SweepArgs::bonds)
 constexpr int kPartials = 9;
+constexpr int kPartialsNoBonds = 3;  // S, Mx, My: what a measurement without bond sums fills
 
 // One lattice of a batch, as the kernels see it.  All offsets are in angle
 // elements (float for FP32, double for FP64).

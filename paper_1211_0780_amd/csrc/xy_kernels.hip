@@ -33,20 +33,22 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Sum the kPartials measurement accumulators over the workgroup in a fixed
-// order and store the item's partials.  Ends with a barrier so the scratch
-// can be reused.
-__device__ __forceinline__ void block_store_partials(const double (&v)[kPartials], double *dst)
+// Sum the first nq measurement accumulators (kPartials with the bond sums,
+// kPartialsNoBonds without) over the workgroup in a fixed order and store
+// the item's partials.  Ends with a barrier so the scratch can be reused.
+__device__ __forceinline__ void block_store_partials(const double (&v)[kPartials], double *dst, int nq)
 {
     __shared__ double red[kBlock / 64][kPartials];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < kPartials; ++q) {
-        const double t = wave_sum(v[q]);
-        if (lane == 0) red[wv][q] = t;
+        if (q < nq) {
+            const double t = wave_sum(v[q]);
+            if (lane == 0) red[wv][q] = t;
+        }
     }
     __syncthreads();
-    if (threadIdx.x < kPartials) {
+    if (threadIdx.x < nq) {
         double acc = 0.0;
         for (int i = 0; i < kBlock / 64; ++i) acc += red[i][threadIdx.x];
         dst[threadIdx.x] = acc;
@@ -507,7 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         }
 
         if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
-        if constexpr (MEAS || KIND == kMeas) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
+        if constexpr (MEAS || KIND == kMeas)
+            block_store_partials(acc, a.partials + kPartials * (int64_t)w, a.bonds ? kPartials : kPartialsNoBonds);
     }
 }
 
@@ -761,7 +764,9 @@ __device__ __forceinline__ void or2_pass(SweepArgs a)
             step(zz, 0, aT1, aT0, aH1, aH0, aO, bT1, bT0, bH1, bH0, bO);
             if (zz + 1 < steps) step(zz + 1, 1, bT1, bT0, bH1, bH0, bO, aT1, aT0, aH1, aH0, aO);
         }
-        if constexpr (MEAS) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
+        if constexpr (MEAS)
+            block_store_partials(acc, a.partials + kPartials * (int64_t)w,
+                                 (BONDS && a.bonds) ? kPartials : kPartialsNoBonds);
     }
 }
 
@@ -882,7 +887,8 @@ __global__ __launch_bounds__(kBlock) void k_plain_f64(SweepArgs a)
         if constexpr (KIND != kMeas) own[q] = nv;
     }
     if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
-    if constexpr (MEAS || KIND == kMeas) block_store_partials(acc, a.partials + kPartials * (int64_t)w);
+    if constexpr (MEAS || KIND == kMeas)
+        block_store_partials(acc, a.partials + kPartials * (int64_t)w, a.bonds ? kPartials : kPartialsNoBonds);
 }
 
 // ---------------------------------------------------------------------------
@@ -945,14 +951,18 @@ __global__ void k_finalize(const LatDev *lats, const double *partials, const dou
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
         for (int r = wv; r < d.R; r += nw) {
             const double *pp = partials + kPartials * ((int64_t)d.item_base + (int64_t)r * d.items_per_slot);
+            // without a bond ring only S, Mx, My were filled and are summed
+            const int nq = bout ? kPartials : kPartialsNoBonds;
             double v[kPartials];
 #pragma unroll
             for (int q = 0; q < kPartials; ++q) v[q] = 0.0;
             for (int it = lane; it < d.items_per_slot; it += 64)
 #pragma unroll
-                for (int q = 0; q < kPartials; ++q) v[q] += pp[kPartials * it + q];
+                for (int q = 0; q < kPartials; ++q)
+                    if (q < nq) v[q] += pp[kPartials * it + q];
 #pragma unroll
-            for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
+            for (int q = 0; q < kPartials; ++q)
+                if (q < nq) v[q] = wave_sum(v[q]);
             if (lane == 0) {
                 const double E = -v[0], mx = v[1], my = v[2];
                 E_slot[pb + r] = E;
