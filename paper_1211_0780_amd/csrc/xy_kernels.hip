@@ -780,7 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
 // loop's usual case).  Without the bond terms the pass needs few enough
 // registers that, capped at 128, four wavefronts fit per SIMD as in the
 // substeps that do not measure (three otherwise): the launch drops from 1.31x
-// to about 1.1x a plain fused substep.  Used for up to three columns per
+// to about 1.06x a plain fused substep.  Used for up to three columns per
 // thread, where the cap costs a few spilled registers outside the inner loop.
 template <int SPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_or2_f32_em(SweepArgs a)
