@@ -48,6 +48,11 @@ struct GraphKey {
 // (exchange after every sweep or never): fewer graph launches, and the gap
 // between consecutive graphs is paid once per batch.
 constexpr int kSweepsPerGraph = 8;
+// Captured graphs kept per context.  Each observable ring is baked into its
+// graphs, so a caller that passes a new ring to every call would otherwise
+// add graphs without bound; beyond this count the oldest graph of another
+// loop shape or ring is released.
+constexpr size_t kMaxGraphs = 32;
 
 struct GraphEntry {
     GraphKey key;
@@ -373,6 +378,8 @@ xy_status check_bad(xy_ctx c)
 
 void free_graphs(xy_ctx c)
 {
+    // a replay may still be in flight on the stream
+    if (!c->graphs.empty()) (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -855,6 +862,18 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
                 *exec = g.exec;
                 return XY_OK;
             }
+        if (c->graphs.size() >= kMaxGraphs) {
+            // release the oldest graph that this call cannot be using
+            for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
+                const GraphKey &k = it->key;
+                if (k.n_metro == n_metro && k.n_or == n_or && k.obs == obs_dev && k.bonds == bonds_dev) continue;
+                (void)hipStreamSynchronize(c->stream);
+                if (it->exec) (void)hipGraphExecDestroy(it->exec);
+                if (it->graph) (void)hipGraphDestroy(it->graph);
+                c->graphs.erase(it);
+                break;
+            }
+        }
         GraphEntry g;
         g.key = key;
         hipStream_t user = c->stream;

@@ -223,6 +223,25 @@ def test_batched_graph_replay_matches_single_sweeps(gpu, exchange_every):
     assert np.array_equal(oa.cpu().numpy(), ob.cpu().numpy())
 
 
+def test_many_rings_release_old_graphs(gpu):
+    """A fresh observable ring on every call captures new graphs; past the
+    context's limit the oldest are released, and the chain is unaffected."""
+    betas = [0.44, 0.45, 0.46]
+    n = 40
+    a = make(8, betas, 3)
+    b = make(8, betas, 3)
+    ob = torch.zeros((n, 3, 5), dtype=torch.float64, device=gpu)
+    b.run(n, 1, 1, exchange_every=1, obs=ob)
+    rings = []
+    for _ in range(n):
+        rings.append(torch.zeros((1, 3, 5), dtype=torch.float64, device=gpu))
+        a.run(1, 1, 1, exchange_every=1, obs=rings[-1])
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.permutation() == b.permutation()
+    assert np.array_equal(torch.cat(rings).cpu().numpy(), ob.cpu().numpy())
+
+
 def test_metropolis_only_sweeps_measure_the_final_state(gpu):
     """With no over-relaxation the sweep ends on a Metropolis half-sweep whose
     near-threshold decisions are re-taken after it; the loop then measures
