@@ -170,7 +170,10 @@ xy_status xy_exchange(xy_ctx ctx, int64_t *n_acc);
  * (sweep index + 1) % exchange_every == 0 }.  exchange_every = 0 disables
  * exchange.  obs_dev: device buffer of n_sweeps*5*R_total doubles, sweep s at
  * offset 5*R_total*s, laid out as xy_measure; may be NULL to skip the copy
- * (observables are still computed for the exchange).  Asynchronous.
+ * (observables are still computed for the exchange).  Graphs are cached per
+ * (n_metro, n_or, obs_dev, bonds ring); reusing a ring reuses its graphs,
+ * and past 32 cached graphs the oldest of other shapes or rings are released
+ * (after the stream has drained).  Asynchronous.
  */
 xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
                  int32_t exchange_every, double *obs_dev);
