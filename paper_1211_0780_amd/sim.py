@@ -76,6 +76,7 @@ class Sim:
         With ``out`` a float64 CUDA tensor of that shape the call stays on the
         device and returns ``out``; otherwise a numpy array is returned."""
         if out is not None:
+            self._check_ring("out", out, self.R_total * 5)
             C.check(C.lib().xy_measure(self._ctx, ctypes.c_void_p(out.data_ptr()), 1), self._ctx)
             return out
         obs = np.zeros((self.R_total, 5), dtype=np.float64)
@@ -95,14 +96,22 @@ class Sim:
         shape (n_sweeps, R_total, 5) receiving every sweep's observables;
         ``bonds`` (optional) one of shape (n_sweeps, R_total, 6) receiving the
         bond sums (C_x, C_y, C_z, I_x, I_y, I_z) of Eq. (6)."""
+        self._check_ring("obs", obs, n_sweeps * self.R_total * 5)
+        self._check_ring("bonds", bonds, n_sweeps * self.R_total * 6)
         ptr = ctypes.c_void_p(obs.data_ptr()) if obs is not None else None
         bptr = ctypes.c_void_p(bonds.data_ptr()) if bonds is not None else None
-        if obs is not None:
-            assert obs.dtype.itemsize == 8 and obs.numel() >= n_sweeps * self.R_total * 5
-        if bonds is not None:
-            assert bonds.dtype.itemsize == 8 and bonds.numel() >= n_sweeps * self.R_total * 6
         C.check(C.lib().xy_run_ex(self._ctx, int(n_sweeps), int(n_metro), int(n_or),
                                   int(exchange_every), ptr, bptr), self._ctx)
+
+    def _check_ring(self, name, t, n):
+        """The kernels write n float64 values through the ring's pointer."""
+        if t is None:
+            return
+        import torch
+        if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        if t.numel() < n:
+            raise ValueError(f"{name} holds {t.numel()} values, the run writes {n}")
 
     def bond_sums(self):
         """(R_total, 6) bond sums C_x, C_y, C_z, I_x, I_y, I_z of the current state."""
@@ -167,7 +176,8 @@ class Sim:
 
     def set_angles(self, theta, lattice=0, beta_pos=0):
         a = np.ascontiguousarray(theta, dtype=np.float64)
-        assert a.size == self.L[lattice] ** 3
+        if a.size != self.L[lattice] ** 3:
+            raise ValueError(f"expected {self.L[lattice] ** 3} angles, got {a.size}")
         C.check(C.lib().xy_set_angles(self._ctx, lattice, beta_pos,
                                       a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
 
