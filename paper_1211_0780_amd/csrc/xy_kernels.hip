@@ -535,12 +535,26 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
 // LDS: P1 = old colour 1 (cos, sin) of plane z on rows y0-2..y0+TY+1 and
 // P0 = new colour 0 of plane z on rows y0-1..y0+TY, both double-buffered.
 // Loads run two planes ahead in alternating register sets, as in
-// k_tile_f32.  MEAS adds the measurement of the new configuration to b
-// (this substep must then be the last of the sweep).
+// k_tile_f32.  MEAS (kOr2Measure, kOr2MeasureBonds) adds the measurement of
+// the new configuration to b (this substep must then be the last of the
+// sweep); kOr2MeasureBonds also forms the bond sums when a.bonds is set.
+//
+// The measuring pass without the bond terms (the production loop's usual
+// case) needs few enough registers that, capped at 128, four wavefronts fit
+// per SIMD as in the substeps that do not measure (three otherwise): the
+// launch drops from 1.31x to about 1.06x a plain fused substep.  The cap is
+// applied only up to three columns per thread, where it costs a few spilled
+// registers outside the inner loop.
 // ---------------------------------------------------------------------------
-template <bool MEAS, bool BONDS, int SPT>
-__device__ __forceinline__ void or2_pass(SweepArgs a)
+enum Or2Measure : int { kOr2Plain = 0, kOr2Measure = 1, kOr2MeasureBonds = 2 };
+
+constexpr int or2_min_waves(int meas, int spt) { return (meas == kOr2Measure && spt <= 3) ? 4 : 1; }
+
+template <int MEAS, int SPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(or2_min_waves(MEAS, SPT))))
+void k_or2_f32(SweepArgs a)
 {
+    constexpr bool BONDS = MEAS == kOr2MeasureBonds;
     extern __shared__ f2 lds[];
     const int tid = threadIdx.x;
 
@@ -723,7 +737,7 @@ __device__ __forceinline__ void or2_pass(SweepArgs a)
                     const float hy = ((c0m2.s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
                     const float nv = overrelax_turns(r1m[s], hx, hy);
                     bstore(nv, r1d, voffT[s], szm);
-                    if constexpr (MEAS) {
+                    if constexpr (MEAS != kOr2Plain) {
                         // colour 1 at (y, z-1) has x = 2j + p, p = (y + z) & 1
                         // (L even keeps the parity through the z wrap); the
                         // same-j neighbour is +x when p = 0, -x when p = 1
@@ -764,29 +778,12 @@ __device__ __forceinline__ void or2_pass(SweepArgs a)
             step(zz, 0, aT1, aT0, aH1, aH0, aO, bT1, bT0, bH1, bH0, bO);
             if (zz + 1 < steps) step(zz + 1, 1, bT1, bT0, bH1, bH0, bO, aT1, aT0, aH1, aH0, aO);
         }
-        if constexpr (MEAS)
+        if constexpr (MEAS != kOr2Plain)
             block_store_partials(acc, a.partials + kPartials * (int64_t)w,
                                  (BONDS && a.bonds) ? kPartials : kPartialsNoBonds);
     }
 }
 
-template <bool MEAS, int SPT>
-__global__ __launch_bounds__(kBlock) void k_or2_f32(SweepArgs a)
-{
-    or2_pass<MEAS, true, SPT>(a);
-}
-
-// The measuring substep when no bond sums are asked for (the production
-// loop's usual case).  Without the bond terms the pass needs few enough
-// registers that, capped at 128, four wavefronts fit per SIMD as in the
-// substeps that do not measure (three otherwise): the launch drops from 1.31x
-// to about 1.06x a plain fused substep.  Used for up to three columns per
-// thread, where the cap costs a few spilled registers outside the inner loop.
-template <int SPT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_or2_f32_em(SweepArgs a)
-{
-    or2_pass<true, false, SPT>(a);
-}
 
 // ---------------------------------------------------------------------------
 // Plain FP64 half-sweep: one thread per site of the updated colour, all six
@@ -1084,7 +1081,7 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int g
     return hipErrorInvalidValue;
 }
 
-template <bool MEAS>
+template <int MEAS>
 static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
                                  int *per_cu)
 {
@@ -1103,16 +1100,9 @@ static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs 
 hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds, const SweepArgs &a,
                           hipStream_t s, int *per_cu)
 {
-    if (fuse_measure && !a.bonds && spt <= 3) {
-        switch (spt) {
-        case 1: return launch_or_query(k_or2_f32_em<1>, grid, lds, a, s, per_cu);
-        case 2: return launch_or_query(k_or2_f32_em<2>, grid, lds, a, s, per_cu);
-        case 3: return launch_or_query(k_or2_f32_em<3>, grid, lds, a, s, per_cu);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    return fuse_measure ? launch_or2_spt<true>(spt, grid, lds, a, s, per_cu)
-                        : launch_or2_spt<false>(spt, grid, lds, a, s, per_cu);
+    if (!fuse_measure) return launch_or2_spt<kOr2Plain>(spt, grid, lds, a, s, per_cu);
+    return a.bonds ? launch_or2_spt<kOr2MeasureBonds>(spt, grid, lds, a, s, per_cu)
+                   : launch_or2_spt<kOr2Measure>(spt, grid, lds, a, s, per_cu);
 }
 
 hipError_t launch_recheck(const SweepArgs &a, hipStream_t s)

@@ -28,7 +28,7 @@ def _counter_csv(path, counter, rows):
             w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
 
 
-@pytest.mark.parametrize("kind,kernel", [("fused", "void xy::k_or2_f32<false, 3>(xy::SweepArgs)"),
+@pytest.mark.parametrize("kind,kernel", [("fused", "void xy::k_or2_f32<0, 3>(xy::SweepArgs)"),
                                          ("half", "void xy::k_tile_f32<1, false, 3, 1>(xy::SweepArgs)")])
 def test_traffic_digest_scales_by_the_copy(tmp_path, monkeypatch, kind, kernel):
     out = tmp_path / f"traffic_{kind}.json"
@@ -57,7 +57,7 @@ def test_traffic_digest_scales_by_the_copy(tmp_path, monkeypatch, kind, kernel):
 def test_traffic_digest_rejects_files_without_the_copy(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "traffic_path", lambda k: str(tmp_path / "t.json"))
     fetch, write = tmp_path / "fetch.csv", tmp_path / "write.csv"
-    kernel = "void xy::k_or2_f32<false, 3>(xy::SweepArgs)"
+    kernel = "void xy::k_or2_f32<0, 3>(xy::SweepArgs)"
     _counter_csv(fetch, "FETCH_SIZE", [(kernel, 3.0)])
     _counter_csv(write, "WRITE_SIZE", [(kernel, 3.0)])
     with pytest.raises(SystemExit):
