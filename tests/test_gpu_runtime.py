@@ -179,6 +179,33 @@ def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     assert np.array_equal(gpu_states(a), gpu_states(b))
 
 
+@pytest.mark.parametrize("tiles", [(8, 8), (16, 8), (24, 8), (48, 6)],
+                         ids=["1col", "2col", "3col", "5col"])
+@pytest.mark.parametrize("with_bonds", [False, True])
+def test_fused_measurement_at_every_column_count(gpu, tiles, with_bonds):
+    """The measuring fused substep (capped to four wavefronts per SIMD at up
+    to three columns per thread when it forms no bond sums) gives the chain,
+    exchanges and observables of the half-sweep path at every column count."""
+    from paper_1211_0780_amd.sim import Sim
+    L, betas, n = 48, [0.44, 0.45, 0.46], 3
+    a = Sim(L, [betas], seed=23, prec="fp32", fused_or=True)
+    b = Sim(L, [betas], seed=23, prec="fp32", fused_or=False)
+    a.set_tiling_fused(0, *tiles)
+    oa = torch.zeros((n, 3, 5), dtype=torch.float64, device=gpu)
+    ob = torch.zeros((n, 3, 5), dtype=torch.float64, device=gpu)
+    ba = torch.zeros((n, 3, 6), dtype=torch.float64, device=gpu) if with_bonds else None
+    bb = torch.zeros((n, 3, 6), dtype=torch.float64, device=gpu) if with_bonds else None
+    a.run(n, 1, 2, exchange_every=1, obs=oa, bonds=ba)
+    b.run(n, 1, 2, exchange_every=1, obs=ob, bonds=bb)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert a.permutation() == b.permutation()
+    # the partial sums group sites differently: equal up to float64 rounding
+    assert np.allclose(oa.cpu().numpy(), ob.cpu().numpy(), rtol=1e-12, atol=1e-9)
+    if with_bonds:
+        assert np.allclose(ba.cpu().numpy(), bb.cpu().numpy(), rtol=1e-12, atol=1e-9)
+
+
 @pytest.mark.parametrize("prec,fused", [("fp32", True), ("fp32", False), ("fp64", False)])
 def test_measurement_without_bond_sums(gpu, prec, fused):
     """A run that records no bond sums skips them in the measurement; the
