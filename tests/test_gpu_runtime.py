@@ -179,6 +179,30 @@ def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     assert np.array_equal(gpu_states(a), gpu_states(b))
 
 
+def test_fused_path_at_its_largest_lattice(gpu):
+    """L = 256 is the largest lattice the fused substep takes (its halo rows
+    fill one entry per thread); a batch with L = 258 falls back to the
+    half-sweep kernels for every substep.  Chains and observables agree with
+    the half-sweep path."""
+    from paper_1211_0780_amd.sim import Sim
+    for Ls in ([256], [258, 8]):
+        betas = [[0.45, 0.46]] + [[0.44]] * (len(Ls) - 1)
+        a = Sim(Ls, betas, seed=29, prec="fp32", fused_or=True)
+        b = Sim(Ls, betas, seed=29, prec="fp32", fused_or=False)
+        R = a.R_total
+        oa = torch.zeros((2, R, 5), dtype=torch.float64, device=gpu)
+        ob = torch.zeros((2, R, 5), dtype=torch.float64, device=gpu)
+        a.run(2, 1, 2, exchange_every=1, obs=oa)
+        b.run(2, 1, 2, exchange_every=1, obs=ob)
+        torch.cuda.synchronize()
+        for l in range(len(Ls)):
+            assert np.array_equal(gpu_states(a, l), gpu_states(b, l)), Ls
+            assert a.permutation(l) == b.permutation(l)
+        assert np.allclose(oa.cpu().numpy(), ob.cpu().numpy(), rtol=1e-12, atol=1e-9)
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("tiles", [(8, 8), (16, 8), (24, 8), (48, 6)],
                          ids=["1col", "2col", "3col", "5col"])
 @pytest.mark.parametrize("with_bonds", [False, True])
