@@ -3,7 +3,8 @@
 Each case plants one mistake in a private copy of the oracle's C source
 (a flipped sign, a dropped neighbour or bond, a transposed index, a wrong RNG
 word or constant), builds it on the CPU, and checks that the fast pins of
-test_oracle_rng / test_oracle_updates / test_oracle_physics fail against it.
+test_oracle_rng / test_oracle_updates / test_oracle_physics / test_oracle_chain
+fail against it.
 """
 import os
 import subprocess
@@ -44,6 +45,43 @@ MUTATIONS = {
                                    "int64_t i0 = odd ? (int64_t)x + "),
     "init_uses_word_1": ("theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[0]);",
                          "theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[1]);"),
+    # the multi-replica chain (Sec. II, Monte Carlo step; Eq. (3))
+    "sweep_uses_beta_0_for_every_position": (
+        "acc += orc_metro_half(th, L, beta[k], seed, t, lat, k, s, window, c);",
+        "acc += orc_metro_half(th, L, beta[0], seed, t, lat, k, s, window, c);"),
+    "run_exchanges_before_measuring": (
+        """        for (int k = 0; k < R; ++k) {
+            double o[5];
+            orc_measure(theta + (int64_t)k * N, L, o);
+            E[k] = o[0];
+            if (obs) memcpy(obs + ((int64_t)s * R + k) * 5, o, sizeof(o));
+        }
+        if (exchange_every > 0 && (s + 1) % exchange_every == 0) {
+            orc_exchange(theta, E, L, R, beta, seed, tau, lat, n_swap_acc);
+            ++tau;
+        }""",
+        """        for (int k = 0; k < R; ++k) {
+            double o[5];
+            orc_measure(theta + (int64_t)k * N, L, o);
+            E[k] = o[0];
+        }
+        if (exchange_every > 0 && (s + 1) % exchange_every == 0) {
+            orc_exchange(theta, E, L, R, beta, seed, tau, lat, n_swap_acc);
+            ++tau;
+        }
+        for (int k = 0; k < R; ++k) {
+            double o[5];
+            orc_measure(theta + (int64_t)k * N, L, o);
+            if (obs) memcpy(obs + ((int64_t)s * R + k) * 5, o, sizeof(o));
+        }"""),
+    "run_exchange_cadence_off_by_one": ("if (exchange_every > 0 && (s + 1) % exchange_every == 0) {",
+                                        "if (exchange_every > 0 && s % exchange_every == 0) {"),
+    "exchange_counts_the_next_pair": ("if (n_acc) n_acc[k] += 1;", "if (n_acc) n_acc[k + 1] += 1;"),
+    "run_sweep_counter_frozen": ("uint32_t t = t0 + (uint32_t)s;", "uint32_t t = t0;"),
+    "run_exchange_counter_frozen": ("            orc_exchange(theta, E, L, R, beta, seed, tau, lat, n_swap_acc);\n            ++tau;",
+                                    "            orc_exchange(theta, E, L, R, beta, seed, tau, lat, n_swap_acc);"),
+    "exchange_swaps_energies_only": ("                    a[i] = b[i];\n                    b[i] = tmp;",
+                                     "                    (void)tmp;"),
 }
 
 
@@ -61,6 +99,7 @@ def test_pins_reject_mutation(name, tmp_path):
     env = dict(os.environ, XY_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         "-m", "not slow", "tests/test_oracle_rng.py",
-                        "tests/test_oracle_updates.py", "tests/test_oracle_physics.py"],
+                        "tests/test_oracle_updates.py", "tests/test_oracle_physics.py",
+                        "tests/test_oracle_chain.py"],
                        env=env, capture_output=True, text=True, cwd=ROOT)
     assert r.returncode == 1, r.stdout[-2000:]
