@@ -230,6 +230,21 @@ xy_status xy_get_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *h
 xy_status xy_get_sites(xy_ctx ctx, int32_t lattice, int32_t beta_pos, int64_t n,
                        const int64_t *sites, double *host);
 
+/*
+ * xy_get_sites for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight monitoring loops and harnesses that
+ * forbid allocation): the same result, bit for bit, with the site list and
+ * the gathered angles staged in a static device array of the library
+ * instead of buffers allocated per call.  n <= XY_NOALLOC_MAX_SITES
+ * (XY_ERR_ARG beyond it).  Every GPU holds one such array (4 MiB) from the
+ * first xy_init on it until the process ends, and every call on that GPU
+ * shares it: calls that overlap in time on one GPU (from several threads or
+ * contexts) race and must be serialised by the caller.  Waits.
+ */
+#define XY_NOALLOC_MAX_SITES (1 << 18)
+xy_status xy_get_sites_noalloc(xy_ctx ctx, int32_t lattice, int32_t beta_pos, int64_t n,
+                               const int64_t *sites, double *host);
+
 /* Overwrite that configuration from host radians (any finite values; they are
  * wrapped into [0, 2pi) and, for FP32, rounded to float32 turns).  Waits. */
 xy_status xy_set_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, const double *host);

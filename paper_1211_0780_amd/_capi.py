@@ -23,7 +23,8 @@ EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange"
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
            "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused",
-           "xy_set_proposal_window", "xy_get_recheck_overflow"]
+           "xy_set_proposal_window", "xy_get_recheck_overflow", "xy_get_sites_noalloc"]
+XY_NOALLOC_MAX_SITES = 1 << 18
 
 
 class XYConfig(ctypes.Structure):
@@ -102,6 +103,8 @@ def lib():
         L.xy_autotune.restype = i32
         L.xy_get_sites.argtypes = [vp, i32, i32, ctypes.c_int64, i64p, dp]
         L.xy_get_sites.restype = i32
+        L.xy_get_sites_noalloc.argtypes = [vp, i32, i32, ctypes.c_int64, i64p, dp]
+        L.xy_get_sites_noalloc.restype = i32
         L.xy_run_ex.argtypes = [vp, i32, i32, i32, i32, vp, vp]
         L.xy_run_ex.restype = i32
         L.xy_get_bond_sums.argtypes = [vp, vp, i32]

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,7 +25,36 @@
 
 using namespace xy;
 
+// Device scratch of the allocation-free sampled read-back
+// (xy_get_sites_noalloc): the site list of one call, then the gathered
+// angles.  One copy per GPU, held until the process ends.  In host code the
+// array's name is only a stand-in: its device address is looked up once per
+// device (scratch_address) and only that address reaches kernels and copies.
+static __device__ __align__(256) unsigned char
+    scratch[(size_t)XY_NOALLOC_MAX_SITES * (sizeof(int64_t) + sizeof(double))];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`: hipGetSymbolAddress with the device
+// current, once per device, the result kept for later contexts.
+hipError_t scratch_address(int dev, void **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 thread_local std::string g_init_error;
 
@@ -121,6 +151,8 @@ struct xy_ctx_s {
     size_t lds2 = 0;
     LatDev *d_lat_or2 = nullptr;
     void *ang2 = nullptr;       // second configuration buffer for the fused kernel
+    int dev = 0;                // device the context was created on
+    void *scratch = nullptr;    // that device's copy of the static scratch array
     std::string err;
 };
 
@@ -649,6 +681,14 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
         hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         c->err = "no HIP device available";
         return bail(XY_ERR_HIP);
+    }
+    c->dev = dev;
+    {
+        const hipError_t e = scratch_address(dev, &c->scratch);
+        if (e != hipSuccess) {
+            c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return bail(XY_ERR_HIP);
+        }
     }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         c->err = "hipStreamCreateWithFlags failed";
@@ -1254,6 +1294,34 @@ xy_status xy_get_sites(xy_ctx c, int32_t lattice, int32_t beta_pos, int64_t n, c
     (void)hipFree(d_sites);
     (void)hipFree(d_out);
     if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("xy_get_sites: ") + hipGetErrorString(e));
+    return XY_OK;
+}
+
+// xy_get_sites without allocating: the site list and the gathered angles are
+// staged in this device's static scratch array instead of per-call buffers.
+xy_status xy_get_sites_noalloc(xy_ctx c, int32_t lattice, int32_t beta_pos, int64_t n,
+                               const int64_t *sites, double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!sites || !host))) return fail(c, XY_ERR_ARG, "bad n or NULL array");
+    if (n > XY_NOALLOC_MAX_SITES)
+        return fail(c, XY_ERR_ARG, "n exceeds the static scratch capacity (XY_NOALLOC_MAX_SITES = 262144 sites)");
+    if (!c->scratch) return fail(c, XY_ERR_STATE, "device scratch address not set up");
+    int slot = 0;
+    xy_status st = slot_of_position(c, lattice, beta_pos, &slot);
+    if (st || n == 0) return st;
+    const LatDev &d = c->lat_sweep[lattice];
+    for (int64_t g = 0; g < n; ++g)
+        if (sites[g] < 0 || sites[g] >= d.N) return fail(c, XY_ERR_ARG, "site index out of range");
+    int64_t *d_sites = (int64_t *)c->scratch;
+    double *d_out = (double *)((char *)c->scratch + (size_t)XY_NOALLOC_MAX_SITES * sizeof(int64_t));
+    hipError_t e = hipMemcpyAsync(d_sites, sites, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_gather(c->prec == XY_FP32, c->ang, d.base + (int64_t)slot * d.N, d.L, n, d_sites, d_out,
+                          c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("xy_get_sites_noalloc: ") + hipGetErrorString(e));
     return XY_OK;
 }
 
