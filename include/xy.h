@@ -146,7 +146,9 @@ xy_status xy_sweep(xy_ctx ctx, int32_t n_metro, int32_t n_or);
  * obs has 5*R_total doubles; if
  * obs_on_device is nonzero it is a device pointer and the call is
  * asynchronous, otherwise it is host memory and the call waits for it.
- * Returns XY_ERR_STATE if any energy is not finite.
+ * Returns XY_ERR_STATE (host destination only) if any energy or
+ * magnetisation measured since the sentinel was last reported is not finite,
+ * and clears the sentinel.
  */
 xy_status xy_measure(xy_ctx ctx, double *obs, int32_t obs_on_device);
 
@@ -173,7 +175,12 @@ xy_status xy_exchange(xy_ctx ctx, int64_t *n_acc);
  * (observables are still computed for the exchange).  Graphs are cached per
  * (n_metro, n_or, obs_dev, bonds ring); reusing a ring reuses its graphs,
  * and past 32 cached graphs the oldest of other shapes or rings are released
- * (after the stream has drained).  Asynchronous.
+ * (after the stream has drained).  Asynchronous.  Failure detection without
+ * waiting: each loop leaves a copy of the device's non-finite sentinel (set
+ * when a measured E, Mx or My is not finite), and the next xy_run or
+ * xy_run_ex returns XY_ERR_STATE (enqueuing nothing) if that copy has
+ * already landed and is set; a report clears the sentinel.  xy_measure into
+ * host memory waits and reports it as well.
  */
 xy_status xy_run(xy_ctx ctx, int32_t n_sweeps, int32_t n_metro, int32_t n_or,
                  int32_t exchange_every, double *obs_dev);
@@ -223,6 +230,17 @@ xy_status xy_set_proposal_window(xy_ctx ctx, double window);
  * configuration at (lattice, beta_pos) to host memory.  Waits. */
 xy_status xy_get_angles(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *host);
 
+/* Diagnostic read of the fused over-relaxation pass (Eq. (2), both colours
+ * per launch, FP32 contexts that use it): the fused substeps of a sweep
+ * alternate between the primary angle buffer and a second library-owned one,
+ * so after a sweep with 2m fused substeps the second buffer holds the
+ * configuration after fused substep 2m-1 (the substep before the last).
+ * Copies that configuration at (lattice, beta_pos) to host radians like
+ * xy_get_angles, letting a caller check a single fused substep site by site.
+ * XY_ERR_UNSUPPORTED for contexts without the fused pass.  Meaningless
+ * before the first such sweep.  Waits. */
+xy_status xy_get_angles_fused_mid(xy_ctx ctx, int32_t lattice, int32_t beta_pos, double *host);
+
 /* The angles (radians) of n chosen sites (natural index i = x + L*(y + L*z),
  * 0 <= i < N_l) of the configuration at (lattice, beta_pos), in order, into
  * host memory; n <= 2^26.  For sampled checks of lattices too large to copy
@@ -262,7 +280,8 @@ xy_status xy_get_metro_accepts(xy_ctx ctx, int64_t *n_acc);
 /*
  * Float64 re-decision queue of the FP32 Metropolis path (Sec. II; the
  * acceptance test of the Metropolis update): sites whose float32 decision
- * lies within 1e-5 of the threshold are queued and decided again in float64.
+ * lies within max(1e-5, 1.6e-5 * beta) of the threshold (eight times the
+ * float32 error of exp(-beta dE)) are queued and decided again in float64.
  * The queue holds max(4096, min(2^22, S / 1000)) entries, S being the sites
  * one half-sweep updates over every lattice and replica (about 2e-5 S land
  * in the band); entries beyond that keep their float32 decision and are

@@ -58,6 +58,9 @@ def lib():
         L.orc_metro_site.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_dbl,
                                      ctypes.c_int64]
         L.orc_metro_site.restype = c_int
+        L.orc_metro_margin.argtypes = [dp, c_int, c_dbl, c_u64, c_u32, c_int, c_int, c_int, c_dbl,
+                                       c_int, dp]
+        L.orc_metro_margin.restype = None
         L.orc_or_site.argtypes = [dp, c_int, ctypes.c_int64]
         L.orc_or_site.restype = None
         L.orc_or_half.argtypes = [dp, c_int, c_int]
@@ -122,6 +125,18 @@ def metro_site(theta, L, beta, seed, t, lat, k, substep, i, window=0.0):
     assert theta.dtype == np.float64 and theta.flags.c_contiguous and theta.size == L ** 3
     return lib().orc_metro_site(_dp(theta), L, float(beta), seed, t, lat, k, substep, float(window),
                                 int(i))
+
+
+def metro_margin(theta, L, beta, seed, t, lat, k, substep, colour, window=0.0):
+    """U(b) - exp(-beta dE) of every site of one colour of a Metropolis
+    half-sweep from ``theta`` (NaN at sites of the other colour); the move is
+    taken where it is negative."""
+    th = _f64(theta)
+    assert th.size == L ** 3
+    out = np.empty(L ** 3, dtype=np.float64)
+    lib().orc_metro_margin(_dp(th), L, float(beta), seed, t, lat, k, substep, float(window),
+                           colour, _dp(out))
+    return out
 
 
 def or_site(theta, L, i):

@@ -132,8 +132,10 @@ void orc_init(double *theta, int L, int R, int lat, uint64_t seed)
  *     accept iff U(b) < exp(-beta * dE)
  * The site update returns 1 if accepted; the half-sweep returns the count.
  * ------------------------------------------------------------------------ */
-int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
-                   int k, int substep, double window, int64_t i)
+/* Proposal theta', acceptance uniform u and dE of the move of site i. */
+static void metro_eval(const double *theta, int L, uint64_t seed, uint32_t t, int lat, int k,
+                       int substep, double window, int64_t i, double *th_prop, double *u_acc,
+                       double *dE_out)
 {
     int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
     int64_t nb[6];
@@ -146,12 +148,21 @@ int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t,
     double th_old = theta[i];
     double th_new = window > 0.0 ? wrap_angle(th_old + window * (orc_uniform(wa) - 0.5))
                                  : TWO_PI * orc_uniform(wa);
-    double u = orc_uniform(wb);
     double dE = 0.0;
     for (int n = 0; n < 6; ++n) {
         double thj = theta[nb[n]];
         dE += cos(th_old - thj) - cos(th_new - thj);
     }
+    *th_prop = th_new;
+    *u_acc = orc_uniform(wb);
+    *dE_out = dE;
+}
+
+int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
+                   int k, int substep, double window, int64_t i)
+{
+    double th_new, u, dE;
+    metro_eval(theta, L, seed, t, lat, k, substep, window, i, &th_new, &u, &dE);
     if (u < exp(-beta * dE)) {
         theta[i] = th_new;
         return 1;
@@ -171,6 +182,33 @@ int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_
                 accepted += orc_metro_site(theta, L, beta, seed, t, lat, k, substep, window, i);
             }
     return accepted;
+}
+
+/* ------------------------------------------------------------------------
+ * Decision margins of one Metropolis half-sweep: for every site i of the
+ * given colour, margin[i] = U(b) - exp(-beta * dE) with the draws and the dE
+ * of orc_metro_site, evaluated on theta as given (sites of one colour do not
+ * interact, so every decision of the half-sweep sees exactly this
+ * configuration; Sec. II, checkerboard decomposition).  The move is taken
+ * iff margin < 0.  Sites of the other colour get NaN.  theta is unchanged.
+ * Used to tell a decision that two correct evaluations may take differently
+ * (|margin| near rounding) from a wrong one.
+ * ------------------------------------------------------------------------ */
+void orc_metro_margin(const double *theta, int L, double beta, uint64_t seed, uint32_t t,
+                      int lat, int k, int substep, double window, int colour, double *margin)
+{
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                int64_t i = x + (int64_t)L * (y + (int64_t)L * z);
+                if (((x + y + z) & 1) != colour) {
+                    margin[i] = NAN;
+                    continue;
+                }
+                double th_new, u, dE;
+                metro_eval(theta, L, seed, t, lat, k, substep, window, i, &th_new, &u, &dE);
+                margin[i] = u - exp(-beta * dE);
+            }
 }
 
 /* ------------------------------------------------------------------------

@@ -16,6 +16,8 @@ int orc_metro_site(double *theta, int L, double beta, uint64_t seed, uint32_t t,
 void orc_or_site(double *theta, int L, int64_t i);
 int64_t orc_metro_half(double *theta, int L, double beta, uint64_t seed, uint32_t t, int lat,
                        int k, int substep, double window, int colour);
+void orc_metro_margin(const double *theta, int L, double beta, uint64_t seed, uint32_t t,
+                      int lat, int k, int substep, double window, int colour, double *margin);
 void orc_or_half(double *theta, int L, int colour);
 void orc_sweep(double *theta, int L, int R, const double *beta, uint64_t seed, uint32_t t,
                int lat, int n_metro, int n_or, double window, int64_t *n_acc);

@@ -23,7 +23,8 @@ EXPORTS = ["xy_angles_bytes", "xy_init", "xy_sweep", "xy_measure", "xy_exchange"
            "xy_get_angles", "xy_set_angles", "xy_get_counters", "xy_get_permutation",
            "xy_get_metro_accepts", "xy_get_state", "xy_set_state", "xy_last_error",
            "xy_destroy", "xy_set_tiling", "xy_get_tiling", "xy_sweep_profiled", "xy_autotune", "xy_get_sites", "xy_run_ex", "xy_get_bond_sums", "xy_get_swap_accepts", "xy_set_tiling_fused", "xy_get_tiling_fused",
-           "xy_set_proposal_window", "xy_get_recheck_overflow", "xy_get_sites_noalloc"]
+           "xy_set_proposal_window", "xy_get_recheck_overflow", "xy_get_sites_noalloc",
+           "xy_get_angles_fused_mid"]
 XY_NOALLOC_MAX_SITES = 1 << 18
 
 
@@ -76,6 +77,8 @@ def lib():
         L.xy_run.restype = i32
         L.xy_get_angles.argtypes = [vp, i32, i32, dp]
         L.xy_get_angles.restype = i32
+        L.xy_get_angles_fused_mid.argtypes = [vp, i32, i32, dp]
+        L.xy_get_angles_fused_mid.restype = i32
         L.xy_set_angles.argtypes = [vp, i32, i32, dp]
         L.xy_set_angles.restype = i32
         L.xy_get_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]

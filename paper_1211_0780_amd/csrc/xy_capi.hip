@@ -131,7 +131,10 @@ struct xy_ctx_s {
     double *d_obs = nullptr;
     double *d_bonds = nullptr;     // [R_total][6] bond sums of the last eager measurement
     unsigned long long *d_macc = nullptr, *d_sacc = nullptr;
-    int *d_bad = nullptr;
+    int *d_bad = nullptr;          // latched by the finalisation on a non-finite observable
+    int *h_bad = nullptr;          // pinned host copy taken at the end of every xy_run
+    hipEvent_t bad_ev = nullptr;   // completes when that copy has landed
+    bool bad_pending = false;      // a copy was enqueued and not yet looked at
     RecheckQueue *d_rq = nullptr;
     RecheckEntry *d_rq_entries = nullptr;
     uint32_t rq_capacity = 0;
@@ -399,13 +402,39 @@ xy_status enqueue_finalize(xy_ctx c, int layout, double *obs, int use_ring, bool
     return XY_OK;
 }
 
+// The non-finite sentinel, once reported, is cleared (stream-ordered) so
+// that it reports again only if a later measurement finds the state bad.
+xy_status clear_bad(xy_ctx c)
+{
+    *c->h_bad = 0;
+    XY_HIP(c, hipMemcpyAsync(c->d_bad, c->h_bad, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    XY_HIP(c, hipStreamSynchronize(c->stream));
+    return XY_OK;
+}
+
 xy_status check_bad(xy_ctx c)
 {
-    int bad = 0;
-    XY_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->bad_pending = false;
+    XY_HIP(c, hipMemcpyAsync(c->h_bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
-    if (bad) return fail(c, XY_ERR_STATE, "non-finite energy or magnetisation in the device state");
+    if (*c->h_bad) {
+        xy_status st = clear_bad(c);
+        if (st) return st;
+        return fail(c, XY_ERR_STATE, "non-finite energy or magnetisation in the device state");
+    }
     return XY_OK;
+}
+
+// Without waiting: if the sentinel copy taken at the end of an earlier
+// xy_run has landed, report (and clear) what it found.
+xy_status poll_bad(xy_ctx c)
+{
+    if (!c->bad_pending || hipEventQuery(c->bad_ev) != hipSuccess) return XY_OK;
+    c->bad_pending = false;
+    if (!*c->h_bad) return XY_OK;
+    xy_status st = clear_bad(c);
+    if (st) return st;
+    return fail(c, XY_ERR_STATE, "non-finite energy or magnetisation found by an earlier xy_run");
 }
 
 void free_graphs(xy_ctx c)
@@ -422,8 +451,16 @@ void free_graphs(xy_ctx c)
 void free_all(xy_ctx c)
 {
     if (!c) return;
-    if (c->stream || c->cap_stream) (void)hipDeviceSynchronize();
+    // wait for this context's own work only (other streams and contexts on
+    // the device keep running)
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != c->dev) (void)hipSetDevice(c->dev);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
     free_graphs(c);
+    if (c->bad_ev) (void)hipEventDestroy(c->bad_ev);
+    if (c->h_bad) (void)hipHostFree(c->h_bad);
     if (c->own_ang && c->ang) (void)hipFree(c->ang);
     void *ptrs[] = {c->d_lat_or2, c->ang2, c->d_lat_sweep, c->d_lat_meas, c->d_beta, c->d_pos, c->d_slot_of, c->d_ctl,
                     c->d_partials, c->d_E, c->d_obs, c->d_bonds, c->d_macc, c->d_sacc, c->d_bad,
@@ -431,6 +468,7 @@ void free_all(xy_ctx c)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (cur >= 0 && cur != c->dev) (void)hipSetDevice(cur);
 }
 
 xy_status validate(const xy_config *cfg)
@@ -716,6 +754,12 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
         (st = dev_alloc(c, &c->d_macc, c->R_total)) || (st = dev_alloc(c, &c->d_sacc, c->R_total)) ||
         (st = dev_alloc(c, &c->d_bad, 1)))
         return bail(st);
+    if (hipHostMalloc((void **)&c->h_bad, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->bad_ev, hipEventDisableTiming) != hipSuccess) {
+        c->err = "pinned host flag or event creation failed";
+        return bail(XY_ERR_HIP);
+    }
+    *c->h_bad = 0;
     // Near-threshold queue: about 2e-5 of a half-sweep's sites land in the band;
     // capacity allows for 1e-3 of the largest lattice's half-sweep.
     {
@@ -890,6 +934,8 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
         return fail(c, XY_ERR_ARG, "need 0 <= n_metro <= 255, 0 <= n_or, n_metro + n_or >= 1");
     if (c->t + (uint64_t)n_sweeps > 0xffffffffull || c->tau + (uint64_t)n_sweeps > 0xffffffffull)
         return fail(c, XY_ERR_STATE, "counters would overflow 32 bits");
+    xy_status st0 = poll_bad(c);
+    if (st0) return st0;
     if (n_sweeps == 0) return XY_OK;
 
     // Captured graphs of `batch` sweeps, each sweep + measure (+ exchange),
@@ -978,6 +1024,10 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
     }
     c->e_fresh = true;
     c->bonds_fresh = false;
+    // the sentinel as this loop leaves it, looked at (without waiting) by the next xy_run
+    XY_HIP(c, hipMemcpyAsync(c->h_bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    XY_HIP(c, hipEventRecord(c->bad_ev, c->stream));
+    c->bad_pending = true;
     return XY_OK;
 }
 
@@ -1241,16 +1291,17 @@ static xy_status slot_of_position(xy_ctx c, int lattice, int beta_pos, int *slot
     return XY_OK;
 }
 
-xy_status xy_get_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, double *host)
+// Natural-order radians of the configuration at (lattice, beta_pos) held in
+// the angle buffer `buf` (the primary one or the fused pass's second one).
+static xy_status read_angles(xy_ctx c, const void *buf, int32_t lattice, int32_t beta_pos, double *host)
 {
-    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
     if (!host) return fail(c, XY_ERR_ARG, "host is NULL");
     int slot = 0;
     xy_status st = slot_of_position(c, lattice, beta_pos, &slot);
     if (st) return st;
     const LatDev &d = c->lat_sweep[lattice];
     std::vector<char> raw((size_t)d.N * c->elem);
-    XY_HIP(c, hipMemcpyAsync(raw.data(), (char *)c->ang + (size_t)(d.base + (int64_t)slot * d.N) * c->elem,
+    XY_HIP(c, hipMemcpyAsync(raw.data(), (const char *)buf + (size_t)(d.base + (int64_t)slot * d.N) * c->elem,
                              raw.size(), hipMemcpyDeviceToHost, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
     const int L = d.L, half = d.half;
@@ -1265,6 +1316,20 @@ xy_status xy_get_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, double *hos
                                                : ((const double *)raw.data())[src];
             }
     return XY_OK;
+}
+
+xy_status xy_get_angles(xy_ctx c, int32_t lattice, int32_t beta_pos, double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    return read_angles(c, c->ang, lattice, beta_pos, host);
+}
+
+xy_status xy_get_angles_fused_mid(xy_ctx c, int32_t lattice, int32_t beta_pos, double *host)
+{
+    if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
+    if (!c->fused_or || !c->ang2)
+        return fail(c, XY_ERR_UNSUPPORTED, "this context does not use the fused over-relaxation");
+    return read_angles(c, c->ang2, lattice, beta_pos, host);
 }
 
 xy_status xy_get_sites(xy_ctx c, int32_t lattice, int32_t beta_pos, int64_t n, const int64_t *sites,

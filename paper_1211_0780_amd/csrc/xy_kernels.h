@@ -38,7 +38,7 @@ struct Ctl {
 };
 
 // Metropolis decisions whose float32 acceptance probability lies within
-// 1e-5 of the uniform are queued here by the FP32 half-sweep and re-taken in
+// max(1e-5, 1.6e-5 beta) of the uniform are queued here by the FP32 half-sweep and re-taken in
 // float64 by a follow-up kernel (same-colour sites do not interact, so the
 // deferral changes nothing).
 struct RecheckEntry {

@@ -295,6 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         const int y0 = ty * TY, z0 = tz * d.TZ;
         const int k = uni(a.pos[d.pos_base + slot]);
         const float beta = __builtin_bit_cast(float, uni(__builtin_bit_cast(int, (float)a.beta[d.pos_base + k])));
+        // Re-decision band: the float32 dE (|dE| <= 12) errs by about 2e-6,
+        // so p = exp(-beta dE) <= 1 errs by up to beta * 2e-6; the band keeps
+        // an 8x margin over that and never drops below 1e-5.
+        const float band = __builtin_fmaxf(1e-5f, 1.6e-5f * beta);
         const uint32_t plane_b = (uint32_t)L * (uint32_t)half * 4u;  // bytes per plane
         const float *angs = (const float *)a.ang + d.base + (int64_t)slot * d.N;
         const __amdgpu_buffer_rsrc_t rown = colour_rsrc(angs + (int64_t)a.colour * (d.N / 2), d.N / 2);
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
                     const float pa = __expf(-beta * dE);
                     const bool acc = u1 < pa;
-                    if (a.recheck && __builtin_fabsf(u1 - pa) < 1e-5f) {
+                    if (a.recheck && __builtin_fabsf(u1 - pa) < band) {
                         const uint32_t idx = atomicAdd(&a.rq->count, 1u);
                         if (idx < a.rq->capacity) {
                             RecheckEntry e;

@@ -71,7 +71,8 @@ def compare(L, betas, n_sweeps=10000, n_metro=1, n_or=8, seeds=(3, 1003), discar
     return {"L": L, "betas": [float(x) for x in betas], "n_sweeps": n_sweeps, "n_metro": n_metro,
             "n_or": n_or, "seeds": list(seeds), "discard": discard,
             "max_abs_z": float(np.max(np.abs(zs))), "mean_z": float(np.mean(zs)),
-            "rms_z": float(np.sqrt(np.mean(zs ** 2))), "n_comparisons": int(zs.size),
+            "rms_z": float(np.sqrt(np.mean(zs ** 2))), "n_compared": int(zs.size),
+            "frac_within_2sigma": float(np.mean(np.abs(zs) <= 2.0)),
             "same_state": same, "per_beta": per_beta}
 
 

@@ -165,6 +165,15 @@ class Sim:
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
         return out
 
+    def get_angles_fused_mid(self, lattice=0, beta_pos=0):
+        """The fused over-relaxation pass's second buffer: after a sweep with
+        2m fused substeps, the configuration after the one before the last."""
+        n = self.L[lattice] ** 3
+        out = np.empty(n, dtype=np.float64)
+        C.check(C.lib().xy_get_angles_fused_mid(self._ctx, lattice, beta_pos,
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
+        return out
+
     def get_sites(self, sites, lattice=0, beta_pos=0):
         """Angles (radians) of the given natural site indices."""
         idx = np.ascontiguousarray(sites, dtype=np.int64)

@@ -1,0 +1,232 @@
+"""Oracle parity at the shapes of the two multi-replica workloads that are
+not the benchmark's: the parallel-tempering ladder (L = 32, 16 replicas over
+beta in [0.450, 0.458], float32 angles, 1 Metropolis + 5 over-relaxation,
+exchange every sweep, seed 2) and the batched finite-size-scaling set
+(L in {24, 32, 48, 64, 96, 128}, 16 replicas each over [0.452, 0.456], one
+launch per half-sweep for the whole batch, autotuned tiles, fused
+over-relaxation), through the C ABI.
+
+Per half-sweep and per fused substep, every site of every checked
+configuration is compared with the oracle's step from the GPU's own state
+(Sec. II: checkerboard Metropolis; Eq. (2): over-relaxation).  Bounds: a
+Metropolis decision may differ from the oracle's only within 1e-6 of the
+threshold, agreeing sites within 2e-5 rad; over-relaxation within
+max(2e-5, 16 * 2^-24 * 6 / |h|) rad.  Exchange decisions (Eq. (3)) and the
+per-pair swap counters must equal the oracle's exactly.  The ladder's
+long-run averages are compared with oracle statistics stored in
+tests/golden/ (written by tests/golden/make_pt_ladder_stats.py, which calls
+only the oracle).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import check_metro_half, check_or_substep, colour_mask, gpu_states
+from stats_util import binder, bins_mean, bins_ratio, bonferroni_z, chain_bins, z_family
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+L_PT, SEED_PT = 32, 2
+BETAS_PT = np.linspace(0.450, 0.458, 16)
+FSS_LS = [24, 32, 48, 64, 96, 128]
+BETAS_FSS = np.linspace(0.452, 0.456, 16)
+SEED_FSS = 5
+
+
+def make(L, betas, seed, **kw):
+    from paper_1211_0780_amd.sim import Sim
+    return Sim(L, betas, seed=seed, prec="fp32", **kw)
+
+
+@pytest.fixture(scope="module")
+def ladder(gpu):
+    s = make(L_PT, [BETAS_PT], SEED_PT)
+    assert s.get_tiling_fused(0) != (0, 0), "the ladder should run the fused over-relaxation"
+    s.run(4, 1, 5, exchange_every=1)   # a few sweeps in, with some swaps taken
+    yield s
+    s.close()
+
+
+def metropolis_substep_every_site(s, lattice, L, betas, seed, positions):
+    """One Metropolis substep (colour 0, then colour 1) of the given
+    beta-positions against the oracle; returns (flips, accepted per position
+    by the oracle, accepted per position by the GPU)."""
+    t = s.counters()[0]
+    before = {k: s.get_angles(lattice, k) for k in positions}
+    acc0 = s.metro_accepts()
+    s.sweep(1, 0)
+    acc1 = s.metro_accepts()
+    m0 = colour_mask(L, 0)
+    flips, ref_acc, gpu_acc = 0, [], []
+    for k in positions:
+        after = s.get_angles(lattice, k)
+        n_ref = 0
+        for c in (0, 1):
+            start = before[k] if c == 0 else np.where(m0, after, before[k])
+            got = np.where(m0, after, before[k]) if c == 0 else after
+            ref = start.copy()
+            n_ref += oracle.metro_half(ref, L, betas[k], seed, t, lattice, k, 0, c)
+            margin = oracle.metro_margin(start, L, betas[k], seed, t, lattice, k, 0, c)
+            flips += check_metro_half(start, got, ref, margin, L, c, 2e-5)
+        ref_acc.append(n_ref)
+        gpu_acc.append(int(acc1[s.pos_base[lattice] + k] - acc0[s.pos_base[lattice] + k]))
+    return flips, np.array(ref_acc), np.array(gpu_acc)
+
+
+def test_ladder_metropolis_every_site_every_replica(ladder):
+    s = ladder
+    flips, ref_acc, gpu_acc = metropolis_substep_every_site(s, 0, L_PT, BETAS_PT, SEED_PT, range(16))
+    print(f"[ladder metropolis] flips {flips}, accepted {gpu_acc.sum()} of {16 * L_PT ** 3}")
+    # the acceptance counters follow the decisions, flipped ones included
+    assert np.all(np.abs(gpu_acc - ref_acc) <= flips)
+    assert s.recheck_overflow() == 0
+
+
+def test_ladder_fused_over_relaxation_every_site(ladder):
+    """Both fused launches of a two-substep sweep, each checked colour by
+    colour against the oracle: the first from the starting configuration (its
+    result read from the fused pass's second buffer), the second from that."""
+    s = ladder
+    before = gpu_states(s)
+    s.sweep(0, 2)
+    worst = 0.0
+    for k in range(16):
+        mid = s.get_angles_fused_mid(0, k)
+        after = s.get_angles(0, k)
+        worst = max(worst, check_or_substep(before[k], mid, L_PT), check_or_substep(mid, after, L_PT))
+    print(f"[ladder fused over-relaxation] largest deviation {worst:.3f} of the per-site bound")
+
+
+def test_ladder_measuring_fused_substep(ladder):
+    """The fused launch that also measures (last substep of a measured sweep):
+    its angles site by site, and its observables against the oracle's
+    measurement of the same configurations."""
+    s = ladder
+    before = gpu_states(s)
+    obs = torch.zeros((1, 16, 5), dtype=torch.float64, device="cuda")
+    s.run(1, 0, 2, exchange_every=0, obs=obs)
+    torch.cuda.synchronize()
+    o = obs[0].cpu().numpy()
+    N = L_PT ** 3
+    for k in range(16):
+        mid = s.get_angles_fused_mid(0, k)
+        after = s.get_angles(0, k)
+        check_or_substep(before[k], mid, L_PT)
+        check_or_substep(mid, after, L_PT)
+        ref = oracle.measure(after, L_PT)
+        assert abs(o[k, 0] - ref[0]) <= 2e-7 * N, (k, o[k, 0], ref[0])
+        assert abs(o[k, 2] - ref[2]) <= 1e-6
+
+
+def test_ladder_exchange_and_swap_counts_match_oracle(gpu):
+    """Sixteen sweeps of the ladder (1 + 5), each followed by measurement and
+    exchange: the GPU's configurations by beta-position after every exchange
+    equal the oracle's exchange applied to the same energies, and the
+    per-pair swap counters equal the oracle's."""
+    s = make(L_PT, [BETAS_PT], SEED_PT)
+    sacc0 = s.swap_accepts()
+    n_ref = np.zeros(16, dtype=np.int64)
+    for step in range(16):
+        s.sweep(1, 5)
+        E = s.measure()[:, 0].copy()
+        tau = s.counters()[1]
+        theta = gpu_states(s)
+        oracle.exchange(theta, E, L_PT, BETAS_PT, SEED_PT, tau, 0, n_acc=n_ref)
+        s.exchange()
+        assert np.array_equal(gpu_states(s), theta), step
+    got = s.swap_accepts() - sacc0
+    print(f"[ladder exchange] swaps per pair {got[:15].tolist()}")
+    assert np.array_equal(got, n_ref)
+    assert n_ref.sum() > 0
+    s.close()
+
+
+def test_ladder_long_run_matches_oracle_statistics(gpu):
+    """10^4 sweeps of the ladder on the GPU (seed 2) against the oracle's
+    pooled chains (other seeds, tests/golden/pt_ladder_L32_oracle.json): per
+    beta-position e, |m|, m^2, m^4 and U_L, gated as one family of 80
+    comparisons at its Bonferroni bound (Phi^-1(1 - 0.025/80) = 3.42)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "pt_ladder_L32_oracle.json")))
+    assert gold["L"] == L_PT and np.allclose(gold["betas"], BETAS_PT)
+    assert gold["n_or"] == 5 and gold["exchange_every"] == 1
+    n = 10000
+    s = make(L_PT, [BETAS_PT], SEED_PT)
+    obs = torch.zeros((n, 16, 5), dtype=torch.float64, device="cuda")
+    s.run(n, 1, 5, exchange_every=1, obs=obs)
+    torch.cuda.synchronize()
+    o = obs.cpu().numpy()
+    pairs, labels = [], []
+    for k in range(16):
+        bins = {c: chain_bins(o[:, k, c], 20, 0.2) for c in (1, 2, 3, 4)}
+        mine = {"e": bins_mean(bins[1]), "abs_m": bins_mean(bins[2]), "m2": bins_mean(bins[3]),
+                "m4": bins_mean(bins[4]), "U_L": bins_ratio(bins[4], bins[3], binder)}
+        for name, (a, ea) in mine.items():
+            b, eb = gold["stats"][k][name]
+            pairs.append((a, ea, b, eb))
+            labels.append((k, name))
+    z, frac2 = z_family(pairs)
+    gate = bonferroni_z(len(pairs))
+    worst = int(np.argmax(np.abs(z)))
+    print(f"[ladder long run vs oracle] max |z| = {abs(z[worst]):.2f} at {labels[worst]}, "
+          f"within 2 sigma: {frac2:.3f} (independent: 0.954), gate {gate:.2f}")
+    assert np.all(np.abs(z) <= gate), [(labels[i], round(float(z[i]), 2)) for i in np.flatnonzero(np.abs(z) > gate)]
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def fss(gpu):
+    s = make(FSS_LS, [BETAS_FSS] * len(FSS_LS), SEED_FSS)
+    s.autotune(1, 10, reps=1)
+    for l in range(len(FSS_LS)):
+        assert s.get_tiling_fused(l) != (0, 0)
+    s.run(2, 1, 10, exchange_every=1)
+    yield s
+    s.close()
+
+
+FSS_CHECK = [(l, k) for l, k in zip(range(len(FSS_LS)), (0, 3, 7, 15, 9, 12))]
+
+
+def test_fss_batch_metropolis_per_lattice(fss):
+    """One configuration of each lattice of the batch (a different
+    beta-position per lattice), every site of both colours of a Metropolis
+    substep that the batch ran in one launch per colour."""
+    s = fss
+    t = s.counters()[0]
+    before = {(l, k): s.get_angles(l, k) for l, k in FSS_CHECK}
+    s.sweep(1, 0)
+    flips = 0
+    for l, k in FSS_CHECK:
+        L = FSS_LS[l]
+        m0 = colour_mask(L, 0)
+        after = s.get_angles(l, k)
+        for c in (0, 1):
+            start = before[(l, k)] if c == 0 else np.where(m0, after, before[(l, k)])
+            got = np.where(m0, after, before[(l, k)]) if c == 0 else after
+            ref = start.copy()
+            oracle.metro_half(ref, L, BETAS_FSS[k], SEED_FSS, t, l, k, 0, c)
+            margin = oracle.metro_margin(start, L, BETAS_FSS[k], SEED_FSS, t, l, k, 0, c)
+            flips += check_metro_half(start, got, ref, margin, L, c, 2e-5)
+    print(f"[fss metropolis] flips {flips}; tiles {[s.get_tiling(l)[:2] for l in range(len(FSS_LS))]}")
+    assert s.recheck_overflow() == 0
+
+
+def test_fss_batch_fused_over_relaxation_per_lattice(fss):
+    """Both fused launches of a two-substep sweep of the whole batch, in the
+    autotuned tiles, for one configuration of each lattice, colour by colour."""
+    s = fss
+    before = {(l, k): s.get_angles(l, k) for l, k in FSS_CHECK}
+    s.sweep(0, 2)
+    worst = {}
+    for l, k in FSS_CHECK:
+        L = FSS_LS[l]
+        mid = s.get_angles_fused_mid(l, k)
+        after = s.get_angles(l, k)
+        worst[L] = round(max(check_or_substep(before[(l, k)], mid, L), check_or_substep(mid, after, L)), 3)
+    print(f"[fss fused over-relaxation] largest deviation per L (units of the bound) {worst}; "
+          f"fused tiles {[s.get_tiling_fused(l) for l in range(len(FSS_LS))]}")

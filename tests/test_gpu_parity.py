@@ -150,25 +150,66 @@ def test_half_sweep_parity(gpu, prec, L, R, tiling):
         assert n_flips == 0
 
 
+def _propagated_sweep_bound(start, L, beta, seed, t):
+    """Per-site bound on |GPU - oracle| after one float32 1 + 1 sweep from the
+    same state.  Metropolis proposals are exact in turns and the float64
+    re-decision leaves no flips beyond 1e-6 of the threshold (checked here on
+    the oracle's own states), so the Metropolis half-sweeps leave identical
+    angles; over-relaxation of colour 0 then errs by at most its per-site
+    bound B0 = max(2e-5, 16 * 2^-24 * 6 / |h|), and colour 1 by its own
+    bound plus the reflection of its neighbours' errors, 2 * sum_j B0_j / |h|.
+    Returns (bound, near-threshold decisions, the oracle's final state)."""
+    st = start.copy()
+    near = 0
+    for c in (0, 1):
+        margin = oracle.metro_margin(st, L, beta, seed, t, 0, 0, 0, c)
+        near += int(np.sum(np.abs(margin[colour_mask(L, c)]) < 1e-6))
+        oracle.metro_half(st, L, beta, seed, t, 0, 0, 0, c)
+    m0 = colour_mask(L, 0)
+    b0 = _or_bound(st, L, "fp32")
+    oracle.or_half(st, L, 0)
+    hx, hy = field_numpy(st, L)
+    h = np.maximum(np.hypot(hx, hy), 1e-30)
+    g = np.where(m0, b0, 0.0).reshape(L, L, L)
+    nb_err = sum(np.roll(g, s_, axis=a) for a in range(3) for s_ in (1, -1)).ravel()
+    b1 = _or_bound(st, L, "fp32") + 2 * nb_err / h
+    oracle.or_half(st, L, 1)
+    return np.where(m0, b0, b1), near, st
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_full_sweeps_match_oracle(gpu, prec):
-    """The single-lattice FP64 chain (L = 8, beta = 0.4542, 1 + 1): ten sweeps, each
-    re-started from the GPU state, against the oracle's sweep."""
+    """The single-lattice chain (L = 8, beta = 0.4542, 1 + 1): ten sweeps, each
+    re-started from the GPU state, against the oracle's sweep.  FP64: every
+    site within 1e-12 rad.  FP32: every site within the bound propagated from
+    the per-half-sweep bounds through the sweep (_propagated_sweep_bound);
+    the maximum and 99.99th percentile of the error are printed."""
     L, seed, beta = 8, 1, 0.4542
     s = make(L, [beta], seed, prec)
-    errs = []
+    errs, ratios = [], []
     for _ in range(10):
         t = s.counters()[0]
         before = s.get_angles()
         s.sweep(1, 1)
+        got = s.get_angles()
         ref = before.reshape(1, -1).copy()
         oracle.sweep(ref, L, [beta], seed, t, 0, 1, 1)
-        errs.append(np.max(circ(s.get_angles(), ref[0])))
+        d = circ(got, ref[0])
+        errs.append(d)
+        if prec == "fp32":
+            bound, near, st = _propagated_sweep_bound(before, L, beta, seed, t)
+            assert np.array_equal(st, ref[0]), "the step-by-step oracle differs from its sweep"
+            if near == 0:
+                ratios.append(float(np.max(d / bound)))
+                assert np.all(d <= bound), (np.max(d / bound), np.argmax(d / bound))
+    allerr = np.concatenate(errs)
+    print(f"[full sweeps {prec}] max {allerr.max():.3g} rad, 99.99th percentile "
+          f"{np.percentile(allerr, 99.99):.3g} rad" +
+          (f", largest error / propagated bound {max(ratios):.3f} over {len(ratios)} sweeps" if ratios else ""))
     if prec == "fp64":
-        assert max(errs) <= 1e-12
+        assert allerr.max() <= 1e-12
     else:
-        # errors propagate through neighbours across four half-sweeps; report-level bound
-        assert np.median(errs) < 1e-3
+        assert len(ratios) >= 8
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -217,7 +258,8 @@ def test_exchange_matches_oracle(gpu, prec):
     betas = list(np.linspace(0.3, 0.6, 6))
     seed = 99
     s = make(L, betas, seed, prec)
-    perm_ref = list(range(len(betas)))
+    n_ref = np.zeros(len(betas), dtype=np.int64)
+    sacc0 = s.swap_accepts()
     for step in range(12):
         s.sweep(1, 1)
         obs = s.measure()
@@ -232,11 +274,13 @@ def test_exchange_matches_oracle(gpu, prec):
                 pytest.skip("decision within 1e-9 of the threshold")
         # the oracle's exchange on the measured energies
         theta = gpu_states(s)
-        oracle.exchange(theta, Ec, L, np.array(betas), seed, tau, 0)
+        oracle.exchange(theta, Ec, L, np.array(betas), seed, tau, 0, n_acc=n_ref)
         s.exchange()
         after = gpu_states(s)
         assert np.array_equal(after, theta)
     assert sorted(s.permutation()) == list(range(len(betas)))
+    # per-pair swap counters (pair (k, k+1) at index k) equal the oracle's
+    assert np.array_equal(s.swap_accepts() - sacc0, n_ref) and n_ref.sum() > 0
 
 
 def test_exchange_counts_and_bijection(gpu):
@@ -350,7 +394,41 @@ def test_windowed_proposal_long_run_matches_oracle(gpu):
     og = obs.cpu().numpy()[:, 0]
     _, oo, _, _ = oracle.run(L, [beta], seed + 1000, n, 1, 1, exchange_every=0, window=w)
     oo = oo[:, 0]
+    from stats_util import bonferroni_z
+    gate = bonferroni_z(2)   # e and m^2: one family of two comparisons
     for c in (1, 3):
         a, ea = binned_mean(og[:, c])
         b, eb = binned_mean(oo[:, c])
-        assert abs(a - b) <= 4 * np.hypot(ea, eb), (c, a, b, ea, eb)
+        z = (a - b) / np.hypot(ea, eb)
+        print(f"[windowed long run] observable {c}: z = {z:.2f} (gate {gate:.2f})")
+        assert abs(z) <= gate, (c, a, b, ea, eb)
+
+
+def test_metropolis_parity_at_large_beta(gpu):
+    """FP32 Metropolis half-sweeps at beta = 3 and 6, where the float32 error
+    of exp(-beta dE) is largest (the re-decision band widens with beta):
+    every site of both colours against the oracle, decisions differing only
+    within 1e-6 of the threshold.  Started from a chain ordered by sweeps at
+    those betas, so that many moves land near the threshold."""
+    from gpu_util import check_metro_half
+    L, seed, betas = 12, 71, [3.0, 6.0]
+    s = make(L, betas, seed, "fp32", start="ordered")
+    s.sweep(1, 1)
+    s.sweep(1, 1)
+    flips = 0
+    for _ in range(3):
+        t = s.counters()[0]
+        before = gpu_states(s)
+        s.sweep(1, 0)
+        after = gpu_states(s)
+        m0 = colour_mask(L, 0)
+        for k, beta in enumerate(betas):
+            for c in (0, 1):
+                start = before[k] if c == 0 else np.where(m0, after[k], before[k])
+                got = np.where(m0, after[k], before[k]) if c == 0 else after[k]
+                ref = start.copy()
+                oracle.metro_half(ref, L, beta, seed, t, 0, k, 0, c)
+                margin = oracle.metro_margin(start, L, beta, seed, t, 0, k, 0, c)
+                flips += check_metro_half(start, got, ref, margin, L, c, 2e-5)
+    print(f"[metropolis beta = 3, 6] near-threshold flips: {flips}")
+    assert s.metro_accepts().sum() > 0

@@ -5,17 +5,19 @@ small parallel-tempering ladder), float32 against float64 kernels on the
 same ladders, exchange on against off, and the Binder crossing of the
 batched finite-size-scaling set.  The two chains of a comparison always run
 from different seeds, so they are independent samples of the same law.
-Averages use binning (20 bins after discarding 20 % as equilibration); two
-runs agree when |a - b| <= Z * sqrt(sa^2 + sb^2), with Z = 4 for every
-family of observables (a Bonferroni-style bound).  The z-scores are printed
-for the record.
+Averages use binning (20 bins after discarding 20 % as equilibration); the
+z-score of a comparison is (a - b) / sqrt(sa^2 + sb^2).  Each test is one
+family of n comparisons (positions x observables) gated at its Bonferroni
+bound Phi^-1(1 - 0.025 / n) (family-wise error 5 %: 2.58 for n = 5, 3.02 for
+20, 3.60 for 160); the largest |z| and the fraction within 2 sigma (about
+0.95 expected for independent comparisons) are printed for the record.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from stats_util import binned_mean, binned_ratio
+from stats_util import binned_mean, binned_ratio, bonferroni_z, z_family
 
 pytestmark = pytest.mark.gpu
 
@@ -42,16 +44,22 @@ def summary(o):
     return out
 
 
-def compare(a, b, Z, label):
-    worst = 0.0
+def compare(a, b, label):
+    """Gate the family of comparisons a vs b at its Bonferroni bound."""
     names = ("e", "|m|", "m2", "m4", "U_L")
+    pairs, labels = [], []
     for p, (ra, rb) in enumerate(zip(a, b)):
         for name, (ma, ea), (mb, eb) in zip(names, ra, rb):
-            z = (ma - mb) / np.hypot(ea, eb)
-            worst = max(worst, abs(z))
-            assert abs(z) <= Z, f"{label} pos {p} {name}: {ma} vs {mb} (z = {z:.2f})"
-    print(f"[{label}] max |z| = {worst:.2f}")
-    return worst
+            pairs.append((ma, ea, mb, eb))
+            labels.append(f"pos {p} {name}")
+    z, frac2 = z_family(pairs)
+    gate = bonferroni_z(len(pairs))
+    worst = int(np.argmax(np.abs(z)))
+    print(f"[{label}] {len(pairs)} comparisons: max |z| = {abs(z[worst]):.2f} ({labels[worst]}), "
+          f"within 2 sigma {frac2:.3f}, gate {gate:.2f}")
+    bad = [f"{labels[i]}: z = {z[i]:.2f}" for i in np.flatnonzero(np.abs(z) > gate)]
+    assert not bad, f"{label}: {bad}"
+    return float(np.abs(z).max())
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -63,7 +71,7 @@ def test_single_lattice_long_run_matches_oracle(gpu, prec):
     s = make(L, [[beta]], seed, prec)
     og = gpu_series(s, n, 1, 1, 0)
     _, oo, _, _ = oracle.run(L, [beta], seed + 1000, n, 1, 1, exchange_every=0)
-    compare(summary(og), summary(oo), 4, f"L=8 {prec} vs oracle")
+    compare(summary(og), summary(oo), f"L=8 {prec} vs oracle")
 
 
 def test_tempering_ladder_long_run_matches_oracle(gpu):
@@ -73,7 +81,7 @@ def test_tempering_ladder_long_run_matches_oracle(gpu):
     s = make(L, [betas], seed)
     og = gpu_series(s, n, 1, 2, 1)
     _, oo, _, sacc = oracle.run(L, betas, seed + 1000, n, 1, 2, exchange_every=1)
-    compare(summary(og), summary(oo), 4, "L=8 PT fp32 vs oracle")
+    compare(summary(og), summary(oo), "L=8 PT fp32 vs oracle")
 
 
 def test_exchange_does_not_change_equilibrium(gpu):
@@ -81,7 +89,7 @@ def test_exchange_does_not_change_equilibrium(gpu):
     betas = list(np.linspace(0.42, 0.48, 6))
     a = gpu_series(make(L, [betas], 11), n, 1, 3, 1)
     b = gpu_series(make(L, [betas], 12), n, 1, 3, 0)
-    compare(summary(a), summary(b), 4, "PT on vs off")
+    compare(summary(a), summary(b), "PT on vs off")
 
 
 def test_fp32_matches_fp64_on_a_ladder(gpu):
@@ -93,8 +101,10 @@ def test_fp32_matches_fp64_on_a_ladder(gpu):
     by both kernel sets."""
     from paper_1211_0780_amd.precision import compare as cmp
     res = cmp(64, np.linspace(0.4530, 0.4554, 32), n_sweeps=2000, seeds=(3, 1003))
-    print(f"[L=64 fp32 vs fp64] max |z| = {res['max_abs_z']:.2f}, rms z = {res['rms_z']:.2f}")
-    assert res["max_abs_z"] <= 4.0
+    gate = bonferroni_z(res["n_compared"])
+    print(f"[L=64 fp32 vs fp64] {res['n_compared']} comparisons: max |z| = {res['max_abs_z']:.2f}, "
+          f"rms z = {res['rms_z']:.2f}, within 2 sigma {res['frac_within_2sigma']:.3f}, gate {gate:.2f}")
+    assert res["max_abs_z"] <= gate
     assert 0.5 <= res["rms_z"] <= 2.0
     for row in res["same_state"]:
         assert row["abs_err_e"] <= 1e-6 and row["abs_err_abs_m"] <= 1e-6

@@ -45,6 +45,9 @@ MUTATIONS = {
                                    "int64_t i0 = odd ? (int64_t)x + "),
     "init_uses_word_1": ("theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[0]);",
                          "theta[(int64_t)k * N + i] = TWO_PI * orc_uniform(r[1]);"),
+    "margin_half_beta": ("margin[i] = u - exp(-beta * dE);", "margin[i] = u - exp(-0.5 * beta * dE);"),
+    "margin_wrong_colour": ("if (((x + y + z) & 1) != colour) {\n                    margin[i] = NAN;",
+                            "if (((x + y + z) & 1) == colour) {\n                    margin[i] = NAN;"),
     # the multi-replica chain (Sec. II, Monte Carlo step; Eq. (3))
     "sweep_uses_beta_0_for_every_position": (
         "acc += orc_metro_half(th, L, beta[k], seed, t, lat, k, s, window, c);",

@@ -249,3 +249,28 @@ def test_windowed_metropolis_proposal_and_decisions(orc):
         else:
             assert th[i] == th0[i]
     assert moved > 0
+
+
+@pytest.mark.parametrize("window", [0.0, 1.3])
+def test_metropolis_margins(orc, window):
+    """orc.metro_margin gives U(b) - exp(-beta dE) for every site of the
+    colour, with the proposal word, the acceptance word and dE rebuilt here
+    from the Python Philox and numpy-rolled fields; NaN on the other colour."""
+    L, seed, t, lat, k, s, beta = 6, 21, 2, 1, 3, 1, 0.55
+    th0 = orc.init(L, 1, seed, lat)[0].copy()
+    key = P.key_of(seed)
+    hx, hy = field(th0, L)
+    hx, hy = hx.ravel(), hy.ravel()
+    for c in (0, 1):
+        m = orc.metro_margin(th0, L, beta, seed, t, lat, k, s, c, window=window)
+        mask = colour_mask(L, c).ravel()
+        assert np.all(np.isnan(m[~mask])) and not np.any(np.isnan(m[mask]))
+        for i in np.flatnonzero(mask):
+            a, b = P.metro_words(int(i), L, t, lat, k, s, key)
+            prop = (th0[i] + window * (P.uniform(a) - 0.5)) % (2 * np.pi) if window else 2 * np.pi * P.uniform(a)
+            dE = (np.cos(th0[i]) - np.cos(prop)) * hx[i] + (np.sin(th0[i]) - np.sin(prop)) * hy[i]
+            assert m[i] == pytest.approx(P.uniform(b) - np.exp(-beta * dE), abs=1e-12), i
+        # and the half-sweep takes exactly the moves with a negative margin
+        th = th0.copy()
+        orc.metro_half(th, L, beta, seed, t, lat, k, s, c, window=window)
+        assert np.array_equal(th[mask] != th0[mask], m[mask] < 0)
