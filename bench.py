@@ -123,17 +123,23 @@ def load_traffic(kernel_hash, kind):
 COPY_BYTES = 1 << 30
 
 
-def traffic_probe(sim, dev):
-    """Workload for `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`: a plain
-    device copy of COPY_BYTES (the calibration kernel: it must read and write
-    exactly that many bytes), then two over-relaxation substeps of the bench
-    configuration (fused: two launches; unfused: four)."""
+def traffic_probe(sim, dev, metro=False):
+    """Workload for `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` and the
+    other counter passes: a plain device copy of COPY_BYTES (the calibration
+    kernel: it must read and write exactly that many bytes), then two
+    over-relaxation substeps of the bench configuration (fused: two launches;
+    unfused: four) or, with `metro`, two Metropolis substeps (four half-sweep
+    launches, each followed by its float64 re-decision launch)."""
     import torch
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    sim.sweep(0, 2)
+    if metro:
+        sim.sweep(1, 0)
+        sim.sweep(1, 0)
+    else:
+        sim.sweep(0, 2)
     torch.cuda.synchronize()
     print("[bench] traffic probe done", file=sys.stderr, flush=True)
 
@@ -204,6 +210,9 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the workload for HBM counter collection: a plain 1 GiB device "
                          "copy, then one over-relaxation substep of the bench configuration")
+    ap.add_argument("--metro-probe", action="store_true",
+                    help="like --traffic-probe, with two Metropolis substeps instead of the "
+                         "over-relaxation")
     ap.add_argument("--digest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs of --traffic-probe into "
                          "profiles/traffic_over_relax_L160x32.json")
@@ -238,8 +247,8 @@ def main():
     tiling_fused = sim.get_tiling_fused(0)
     if args.window > 0:
         sim.set_proposal_window(args.window)
-    if args.traffic_probe:
-        traffic_probe(sim, dev)
+    if args.traffic_probe or args.metro_probe:
+        traffic_probe(sim, dev, metro=args.metro_probe)
         return
     obs = torch.zeros((max(args.steps, args.warmup, 1), R, 5), dtype=torch.float64, device=dev)
 

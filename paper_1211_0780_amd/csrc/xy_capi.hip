@@ -212,6 +212,22 @@ Tiling default_tiling(int L, int R)
     return t;
 }
 
+// LDS of the fused over-relaxation kernel for a tile of ty rows of L/2
+// sites: two old-colour-1 plane buffers of the kernel's fixed size
+// (spt + 2) * kBlock and three new-colour-0 plane buffers of (ty + 2) * L/2
+// (cos, sin) pairs.  Tiles are limited to five columns per thread, so that
+// any batch of admissible tiles fits 64 KiB ((5 * 5 + 7) * kBlock pairs).
+size_t or2_lds_bytes(int ty, int half)
+{
+    const int spt = spt_for(ty * half);
+    return ((size_t)2 * (spt + 2) * kBlock + (size_t)3 * (ty + 2) * half) * 2 * sizeof(float);
+}
+
+bool or2_tile_ok(int ty, int half)
+{
+    return ty * half <= 5 * kBlock && or2_lds_bytes(ty, half) <= kMaxLds;
+}
+
 // Default tile of the fused over-relaxation kernel: up to three tile columns
 // per thread and z-chunks of at most 40 planes (measured best at L = 160).
 Tiling default_tiling2(int L)
@@ -219,7 +235,7 @@ Tiling default_tiling2(int L)
     const int half = L / 2;
     Tiling t;
     for (int d : divisors(L))
-        if (d * half <= 3 * kBlock && (size_t)(5 * d + 14) * half * 2 * sizeof(float) <= kMaxLds) t.TY = d;
+        if (d * half <= 3 * kBlock && or2_tile_ok(d, half)) t.TY = d;
     if (t.TY == 0) t.TY = 1;
     t.TZ = 1;
     for (int d : divisors(L))
@@ -239,17 +255,18 @@ xy_status sync_stream(xy_ctx c)
 // kernel's resident workgroups per CU), each taking items in turn.  Measured
 // at L = 160 x 32, launches sized to the resident capacity beat one
 // workgroup per item by 3-5 % (no half-empty last round of workgroups).
-int launch_grid(xy_ctx c, int items, bool fused, int kind, bool meas, int spt, size_t lds, const SweepArgs &a)
+int launch_grid(xy_ctx c, int items, bool fused, int kind, bool meas, bool full, int spt, size_t lds,
+                const SweepArgs &a)
 {
     if (c->grid_sweep > 0) return std::min(items, c->grid_sweep);
     const uint64_t key = ((uint64_t)lds << 32) | ((uint64_t)fused << 24) | ((uint64_t)c->halo << 16) |
-                         ((uint64_t)spt << 8) | ((uint64_t)(a.bonds != 0) << 5) | ((uint64_t)meas << 4) |
-                         (uint64_t)kind;
+                         ((uint64_t)spt << 8) | ((uint64_t)full << 6) | ((uint64_t)(a.bonds != 0) << 5) |
+                         ((uint64_t)meas << 4) | (uint64_t)kind;
     auto it = c->per_cu.find(key);
     if (it == c->per_cu.end()) {
         int n = 0;
-        const hipError_t e = fused ? launch_or2_f32(meas, spt, 0, lds, a, c->stream, &n)
-                                   : launch_tile_f32(kind, meas, spt, c->halo, 0, lds, a, c->stream, &n);
+        const hipError_t e = fused ? launch_or2_f32(meas, full, spt, 0, lds, a, c->stream, &n)
+                                   : launch_tile_f32(kind, meas, full, spt, c->halo, 0, lds, a, c->stream, &n);
         it = c->per_cu.emplace(key, e == hipSuccess ? n : 0).first;
     }
     const int resident = c->n_cu * it->second;
@@ -280,8 +297,11 @@ xy_status launch_half(xy_ctx c, int kind, int colour, int substep, bool fuse_mea
         const bool meas_item_space = (kind == kMeas);
         a.lats = meas_item_space ? c->d_lat_meas : c->d_lat_sweep;
         a.total_items = meas_item_space ? c->items_meas : c->items_sweep;
-        const int grid = launch_grid(c, a.total_items, false, kind, fuse_measure, c->spt, c->lds_bytes, a);
-        e = launch_tile_f32(kind, fuse_measure, c->spt, c->halo, grid, c->lds_bytes, a, c->stream);
+        // every lattice's tile exactly fills the columns of the launch
+        bool full = !meas_item_space;
+        for (const LatDev &d : c->lat_sweep) full = full && d.TY * d.half == c->spt * kBlock;
+        const int grid = launch_grid(c, a.total_items, false, kind, fuse_measure, full, c->spt, c->lds_bytes, a);
+        e = launch_tile_f32(kind, fuse_measure, full, c->spt, c->halo, grid, c->lds_bytes, a, c->stream);
         if (e == hipSuccess && kind == kMetro && a.recheck) e = launch_recheck(a, c->stream);
     } else {
         a.lats = c->d_lat_sweep;
@@ -310,8 +330,11 @@ xy_status launch_or2(xy_ctx c, void *from, void *to, bool fuse_measure, bool bon
     a.bonds = bonds ? 1 : 0;
     a.macc = c->d_macc;
     a.rq = c->d_rq;
-    const int grid = launch_grid(c, a.total_items, true, 0, fuse_measure, c->spt2, c->lds2, a);
-    hipError_t e = launch_or2_f32(fuse_measure, c->spt2, grid, c->lds2, a, c->stream);
+    // the first spt2 - 1 tile columns of every lattice are populated
+    bool lead = true;
+    for (const LatDev &d : c->lat_or2) lead = lead && d.TY * d.half > (c->spt2 - 1) * kBlock;
+    const int grid = launch_grid(c, a.total_items, true, 0, fuse_measure, lead, c->spt2, c->lds2, a);
+    hipError_t e = launch_or2_f32(fuse_measure, lead, c->spt2, grid, c->lds2, a, c->stream);
     if (e != hipSuccess) return fail(c, XY_ERR_HIP, std::string("fused launch: ") + hipGetErrorString(e));
     return XY_OK;
 }
@@ -534,7 +557,6 @@ void build_layout(xy_ctx c)
     int pos_base = 0, item_s = 0, item_m = 0;
     c->spt = 1;
     c->halo = 1;
-    int max_rowbuf = 0;
     c->lat_sweep.clear();
     c->lat_meas.clear();
     for (int l = 0; l < c->n_lat; ++l) {
@@ -556,7 +578,6 @@ void build_layout(xy_ctx c)
             d.items_per_slot = d.ny * d.nz;
             c->spt = std::max(c->spt, t.spt);
             if (d.L > kBlock) c->halo = 4;
-            max_rowbuf = std::max(max_rowbuf, (t.TY + 2) * d.half);
         } else {
             d.TY = d.TZ = d.ny = d.nz = 0;
             d.items_per_slot = (int)((d.N / 2 + kBlock - 1) / kBlock);
@@ -580,6 +601,7 @@ void build_layout(xy_ctx c)
     c->lds2 = 0;
     if (c->fused_or) {
         int item2 = 0;
+        size_t p0_elems = 0;
         for (int l = 0; l < c->n_lat; ++l) {
             if ((int)c->tiles2.size() <= l) c->tiles2.push_back(default_tiling2(c->L[l]));
             const Tiling t = c->tiles2[l];
@@ -593,11 +615,16 @@ void build_layout(xy_ctx c)
             item2 += d.R * d.items_per_slot;
             c->lat_or2.push_back(d);
             c->spt2 = std::max(c->spt2, t.spt);
-            c->lds2 = std::max(c->lds2, (size_t)(2 * (t.TY + 4) + 3 * (t.TY + 2)) * d.half * 2 * sizeof(float));
+            p0_elems = std::max(p0_elems, (size_t)(t.TY + 2) * d.half);
         }
+        // two old-colour-1 plane buffers at the kernel's fixed size (spt2 + 2) * kBlock,
+        // a bound on (TY + 4) * L/2, then three new-colour-0 plane buffers
+        c->lds2 = ((size_t)2 * (c->spt2 + 2) * kBlock + 3 * p0_elems) * 2 * sizeof(float);
         c->items_or2 = item2;
     }
-    c->lds_bytes = (size_t)2 * max_rowbuf * 2 * sizeof(float);  // two planes of (cos, sin)
+    // two plane buffers of (cos, sin), the second at the kernel's fixed offset
+    // (spt + halo) * kBlock elements, which bounds (TY + 2) * L/2 for every lattice
+    c->lds_bytes = (size_t)2 * (c->spt + c->halo) * kBlock * 2 * sizeof(float);
 }
 
 // Re-derive item spaces after a tiling change and upload them.  Partials
@@ -1172,9 +1199,8 @@ xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
     const int L = c->L[lattice];
     if (ty < 1 || tz < 1 || L % ty != 0 || L % tz != 0)
         return fail(c, XY_ERR_ARG, "ty and tz must divide L");
-    if (ty * (L / 2) > 8 * kBlock) return fail(c, XY_ERR_ARG, "ty * L/2 must be <= 2048");
-    if ((size_t)(5 * ty + 14) * (L / 2) * 2 * sizeof(float) > kMaxLds)
-        return fail(c, XY_ERR_ARG, "tile needs more than 64 KiB of LDS");
+    if (!or2_tile_ok(ty, L / 2))
+        return fail(c, XY_ERR_ARG, "fused tile needs ty * L/2 <= 1280 and at most 64 KiB of LDS");
     Tiling t;
     t.TY = ty;
     t.TZ = tz;

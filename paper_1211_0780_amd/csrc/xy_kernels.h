@@ -38,14 +38,14 @@ struct Ctl {
 };
 
 // Metropolis decisions whose float32 acceptance probability lies within
-// max(1e-5, 1.6e-5 beta) of the uniform are queued here by the FP32 half-sweep and re-taken in
-// float64 by a follow-up kernel (same-colour sites do not interact, so the
-// deferral changes nothing).
+// max(1e-5, 1.6e-5 beta) of the uniform are queued here by the FP32
+// half-sweep and re-taken in float64 by a follow-up kernel (same-colour sites
+// do not interact, so the deferral changes nothing).  The follow-up draws the
+// site's proposal and uniform again from the same Philox counter.
 struct RecheckEntry {
-    int32_t li, slot, q;   // lattice, storage slot, index within the colour array
-    float cur, prop, u1;   // old angle, proposal (turns), acceptance uniform
-    int32_t fp32_accept;   // decision already applied by the half-sweep
-    int32_t pad_;
+    int32_t li, slot;      // lattice, storage slot
+    uint32_t q;            // index within the colour array; bit 31: the float32 decision (accepted)
+    float cur;             // old angle (turns)
 };
 
 struct RecheckQueue {
@@ -80,9 +80,11 @@ struct SweepArgs {
 // Launchers (stream-ordered, no synchronisation).
 // With per_cu non-null the tiled launchers launch nothing and report in
 // *per_cu how many workgroups of the selected kernel fit on one CU.
-hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid,
+// full: every lattice of the launch fills its tile exactly (TY * L/2 = spt * kBlock)
+hipError_t launch_tile_f32(int kind, bool fuse_measure, bool full, int spt, int halo, int grid,
                            size_t lds_bytes, const SweepArgs &a, hipStream_t s, int *per_cu = nullptr);
-hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
+// lead: every lattice of the launch fills the first spt - 1 tile columns (TY * L/2 > (spt - 1) * kBlock)
+hipError_t launch_or2_f32(bool fuse_measure, bool lead, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
                           hipStream_t s, int *per_cu = nullptr);
 hipError_t launch_recheck(const SweepArgs &a, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);

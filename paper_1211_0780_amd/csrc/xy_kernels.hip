@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "xy_device.h"
 #include "xy_kernels.h"
 
@@ -194,10 +196,12 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32
 }
 
 // ---------------------------------------------------------------------------
-// Re-take one queued near-threshold Metropolis decision in float64: the six
-// neighbour angles (other colour, untouched by this half-sweep) are read
-// again, dE and exp(-beta dE) evaluated in double, and the site is corrected
-// where the float64 decision differs.
+// Re-take one queued near-threshold Metropolis decision in float64: the
+// site's proposal and acceptance uniform are drawn again from its Philox
+// counter (the same block and words as the half-sweep), the six neighbour
+// angles (other colour, untouched by this half-sweep) are read again, dE and
+// exp(-beta dE) evaluated in double, and the site is corrected where the
+// float64 decision differs.
 // ---------------------------------------------------------------------------
 __device__ void recheck_entry(const SweepArgs &a, const RecheckEntry &en)
 {
@@ -205,13 +209,26 @@ __device__ void recheck_entry(const SweepArgs &a, const RecheckEntry &en)
     const LatDev d = a.lats[en.li];
     const int L = d.L, half = d.half;
     const int64_t plane = (int64_t)L * half;
-    const int z = (int)(en.q / plane);
-    const int rem = (int)(en.q - (int64_t)z * plane);
+    const uint32_t q = en.q & 0x7fffffffu;
+    const int fp32_accept = (int)(en.q >> 31);
+    const int z = (int)(q / plane);
+    const int rem = (int)(q - (int64_t)z * plane);
     const int y = rem / half, j = rem - y * half;
     const int p = (a.colour + y + z) & 1;
     float *angs = (float *)a.ang + d.base + (int64_t)en.slot * d.N;
     float *own = angs + (int64_t)a.colour * (d.N / 2);
     const float *oth = angs + (int64_t)(a.colour ^ 1) * (d.N / 2);
+    const int k = a.pos[d.pos_base + en.slot];
+    // the pair's block: counter word 0 is the even-plane site of this column
+    const uint32_t zb = (uint32_t)(z & ~1);
+    const uint32_t pb = (uint32_t)p ^ (uint32_t)(z & 1);
+    const uint32_t ib = 2u * (uint32_t)j + pb + (uint32_t)L * ((uint32_t)y + (uint32_t)L * zb);
+    const u32x4 r = philox4x32_10(ib, a.ctl->t, ((uint32_t)d.lat << 16) | (uint32_t)k,
+                                  (kPhaseMetro << 24) | (uint32_t)a.substep, a.k0, a.k1);
+    const uint32_t w0 = (z & 1) ? r.z : r.x, w1 = (z & 1) ? r.w : r.y;
+    // the proposal exactly as the float32 half-sweep formed it (turns)
+    const float u0 = unit24f(w0);
+    const float prop = a.window_t > 0.0f ? frac_turn(__builtin_fmaf(a.window_t, u0 - 0.5f, en.cur)) : u0;
     const int ym = (y == 0) ? L - 1 : y - 1, yp = (y + 1 == L) ? 0 : y + 1;
     const int zm = (z == 0) ? L - 1 : z - 1, zp = (z + 1 == L) ? 0 : z + 1;
     const int jx = p ? ((j + 1 == half) ? 0 : j + 1) : ((j == 0) ? half - 1 : j - 1);
@@ -229,12 +246,11 @@ __device__ void recheck_entry(const SweepArgs &a, const RecheckEntry &en)
     }
     double so, co, sp, cp;
     sincos((double)en.cur * twopi, &so, &co);
-    sincos((double)en.prop * twopi, &sp, &cp);
+    sincos((double)prop * twopi, &sp, &cp);
     const double dE = (co - cp) * hx + (so - sp) * hy;
-    const int k = a.pos[d.pos_base + en.slot];
-    const bool acc = (double)en.u1 < exp(-a.beta[d.pos_base + k] * dE);
-    if ((int)acc != en.fp32_accept) {
-        own[en.q] = acc ? en.prop : en.cur;
+    const bool acc = unit24d(w1) < exp(-a.beta[d.pos_base + k] * dE);
+    if ((int)acc != fp32_accept) {
+        own[q] = acc ? prop : en.cur;
         atomicAdd(a.macc + d.pos_base + k, acc ? 1ull : ~0ull);  // +1 or -1
     }
 }
@@ -265,19 +281,30 @@ __global__ __launch_bounds__(kBlock) void k_recheck(SweepArgs a)
 // per plane, turned into (cos, sin) once, kept in registers for the z
 // neighbours (planes z-1, z+1 of the same column) and staged in LDS (plane
 // z plus one halo row above and below the tile, double-buffered) for the
-// x and y neighbours.  The loop body is straight-line: lanes past the end of
-// the tile shadow column 0 (same loads, same values) and only their stores
-// are masked, so the next plane's loads stay in flight while this plane is
-// computed.
+// x and y neighbours.  The next plane's loads are issued at the top of each
+// plane step and stay in flight while this plane is computed.
 //
 // KIND = kMetro / kOver updates colour a.colour; kMeas (colour 1) only
 // measures.  MEAS accumulates S = sum_{i in colour 1} S_i . h_i (every
 // bond has exactly one colour-1 end, E = -S), M = sum over both colours and,
 // with a.bonds, the bond sums into the item's partials.  HALO = halo entries
-// per thread (2*(L/2) <= HALO*kBlock).
+// per thread (2*(L/2) <= HALO*kBlock).  FULL: every lattice of the launch
+// fills its tile exactly (TY * L/2 = SPT * kBlock), so no column needs a
+// guard.
 // ---------------------------------------------------------------------------
-template <int KIND, bool MEAS, int SPT, int HALO>
-__global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
+// Elements of one plane buffer of the tiled kernel: TY * L/2 <= SPT * kBlock
+// tile sites and 2 * L/2 <= HALO * kBlock halo sites.
+template <int SPT, int HALO>
+constexpr int kTileBufElems = (SPT + HALO) * kBlock;
+
+// The Metropolis half-sweep interleaves its columns' draws, which left to
+// itself the compiler pays for with registers (194 at five columns per
+// thread, two wavefronts per SIMD); capped, three wavefronts fit.
+constexpr int tile_min_waves(int kind, bool meas, int spt) { return (kind == kMetro && !meas && spt <= 5) ? 3 : 1; }
+
+template <int KIND, bool MEAS, int SPT, int HALO, bool FULL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tile_min_waves(KIND, MEAS, SPT))))
+void k_tile_f32(SweepArgs a)
 {
     extern __shared__ f2 lds[];
     const int tid = threadIdx.x;
@@ -299,14 +326,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         // so p = exp(-beta dE) <= 1 errs by up to beta * 2e-6; the band keeps
         // an 8x margin over that and never drops below 1e-5.
         const float band = __builtin_fmaxf(1e-5f, 1.6e-5f * beta);
+        // exp(-beta dE) = 2^(dE * nbl2e)
+        const float nbl2e = -beta * 1.44269504088896341f;
         const uint32_t plane_b = (uint32_t)L * (uint32_t)half * 4u;  // bytes per plane
         const float *angs = (const float *)a.ang + d.base + (int64_t)slot * d.N;
         const __amdgpu_buffer_rsrc_t rown = colour_rsrc(angs + (int64_t)a.colour * (d.N / 2), d.N / 2);
         const __amdgpu_buffer_rsrc_t roth = colour_rsrc(angs + (int64_t)(a.colour ^ 1) * (d.N / 2), d.N / 2);
         const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(angs, 0);
         const int nsite = TY * half;
+        // the second plane buffer at a compile-time offset (a bound on
+        // (TY + 2) * L/2 for every lattice of the launch), so that the
+        // alternating steps address it through immediate LDS offsets
         f2 *buf0 = lds;
-        f2 *buf1 = lds + (TY + 2) * half;
+        f2 *buf1 = lds + kTileBufElems<SPT, HALO>;
         const uint32_t LL = (uint32_t)L * (uint32_t)L;
         const uint32_t c2 = ((uint32_t)d.lat << 16) | (uint32_t)k;
         const uint32_t c3 = (kPhaseMetro << 24) | (uint32_t)a.substep;
@@ -382,17 +414,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
         double acc[kPartials];
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
-        unsigned long long nacc = 0;
-        uint32_t kept0[SPT], kept1[SPT];  // Metropolis: words 2, 3 of the pair's Philox block
+        uint32_t nacc_w = 0;  // accepted moves of this wavefront in this item (wave-uniform)
+        uint32_t kept0[SPT] = {}, kept1[SPT] = {};  // Metropolis: words 2, 3 of the pair's Philox block
 
         // One plane.  pre_* were loaded one step ago and are consumed at the
         // end of this step; nxt_* are issued now and consumed next step.  The
         // loop below alternates the two register sets (and the two LDS
         // buffers) so that no in-flight load is ever copied between registers,
-        // which would force the wait early.
-        auto step = [&](const int zz, const f2 *bc, f2 *bn, const int (&lx)[SPT], float (&pre_o)[SPT],
-                        float (&pre_c)[SPT], float (&pre_h)[HALO], float (&nxt_o)[SPT],
-                        float (&nxt_c)[SPT], float (&nxt_h)[HALO]) {
+        // which would force the wait early.  With FULL the per-column guards
+        // drop out and the compiler may interleave the columns.
+        auto step = [&](const int zz, const f2 *bc, f2 *bn, const int (&lx)[SPT],
+                        float (&pre_o)[SPT], float (&pre_c)[SPT], float (&pre_h)[HALO], float (&nxt_o)[SPT],
+                        float (&nxt_c)[SPT], float (&nxt_h)[HALO]) __attribute__((always_inline)) {
             const int z = z0 + zz;
             const uint32_t sz = (uint32_t)z * plane_b;
             {
@@ -413,12 +446,115 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 for (int h = 0; h < HALO; ++h) nxt_h[h] = bload(ro, hvoff[h], s2);
             }
 
+            if constexpr (KIND == kMetro && !MEAS) {
+                // Metropolis: first the draws of every column (independent
+                // Philox chains the compiler may interleave), then the
+                // decisions column by column, then, rarely, the queue of
+                // near-threshold decisions for the float64 re-decision.
+                // One Philox block per pair of planes (2m, 2m+1) of a column:
+                // drawn at the even plane (or at the tile's first plane when
+                // that is odd), its last two words kept for the odd plane.
+                uint32_t w0[SPT] = {}, w1[SPT] = {};
+                if ((z & 1) == 0 || zz == 0) {
+                    const int zb = z & ~1;
+#pragma unroll
+                    for (int s = 0; s < SPT; ++s) {
+                        if (!FULL && !ok[s]) continue;
+                        const uint32_t pb = (uint32_t)((ypar[s] + zb) & 1);
+                        const uint32_t ib = ibase[s] + pb + LL * (uint32_t)zb;
+                        const u32x4 r = philox4x32_10(ib, t_sweep, c2, c3, a.k0, a.k1);
+                        w0[s] = (z & 1) ? r.z : r.x;
+                        w1[s] = (z & 1) ? r.w : r.y;
+                        kept0[s] = r.z;
+                        kept1[s] = r.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < SPT; ++s) {
+                        w0[s] = kept0[s];
+                        w1[s] = kept1[s];
+                    }
+                }
+                // One column's decision: the field from the staged neighbours,
+                // the proposal, dE and p = exp(-beta dE) (also used, rarely,
+                // to queue a decision: the same arithmetic again, so the same
+                // values).
+                struct Eval {
+                    float prop, u1, pa;
+                };
+                auto eval = [&](auto win_tag, const int s) __attribute__((always_inline)) {
+                    const f2 n1 = bc[lc[s] - half];
+                    const f2 n2 = bc[lc[s] + half];
+                    const f2 n3 = bc[lc[s]];
+                    const f2 n4 = bc[lx[s]];
+                    // plane z-1 of this column: still in the other buffer, which
+                    // this lane overwrites with plane z+1 only at the end of the step
+                    const f2 om = bn[lc[s]];
+                    const float hx = ((om.c + ocp[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
+                    const float hy = ((om.s + ocp[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
+                    Eval v;
+                    // uniform proposal (exact in turns) or theta + w (u0 - 1/2)
+                    v.prop = unit24f(w0[s]);
+                    if constexpr (decltype(win_tag)::value)
+                        v.prop = frac_turn(__builtin_fmaf(a.window_t, v.prop - 0.5f, cur[s]));
+                    v.u1 = unit24f(w1[s]);
+                    const f2 so = sincos_turns(cur[s]);
+                    const f2 sn = sincos_turns(v.prop);
+                    const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
+                    v.pa = __builtin_amdgcn_exp2f(dE * nbl2e);
+                    return v;
+                };
+                // smallest |u - p| over the columns: a decision within the
+                // band anywhere in the wave sends it down the queueing path
+                float closest = 1.0f;
+                auto column = [&](auto win_tag, const int s) __attribute__((always_inline)) {
+                    const Eval v = eval(win_tag, s);
+                    const bool acc = v.u1 < v.pa;
+                    bstore(acc ? v.prop : cur[s], rown, voff[s], sz);
+                    nacc_w += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(acc));
+                    closest = __builtin_fminf(closest, __builtin_fabsf(v.u1 - v.pa));
+                };
+                // near-threshold decisions of the step, queued for the float64
+                // re-decision, which draws the proposal and the uniform again
+                // from the same counter; it needs the old angle and the float32
+                // decision
+                auto queue = [&](auto win_tag) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int s = 0; s < SPT; ++s) {
+                        if (!FULL && !ok[s]) continue;
+                        const Eval v = eval(win_tag, s);
+                        if (!(__builtin_fabsf(v.u1 - v.pa) < band)) continue;
+                        const uint32_t idx = atomicAdd(&a.rq->count, 1u);
+                        if (idx < a.rq->capacity) {
+                            RecheckEntry e;
+                            e.li = li;
+                            e.slot = slot;
+                            e.q = ((sz + voff[s]) >> 2) | ((v.u1 < v.pa ? 1u : 0u) << 31);
+                            e.cur = cur[s];
+                            a.rq->entries[idx] = e;
+                        } else {
+                            atomicAdd(&a.rq->overflow, 1u);
+                        }
+                    }
+                };
+                if (a.window_t > 0.0f) {
+#pragma unroll
+                    for (int s = 0; s < SPT; ++s)
+                        if (FULL || ok[s]) column(std::true_type{}, s);
+                    if (a.recheck && __builtin_amdgcn_ballot_w64(closest < band) != 0) queue(std::true_type{});
+                } else {
+#pragma unroll
+                    for (int s = 0; s < SPT; ++s)
+                        if (FULL || ok[s]) column(std::false_type{}, s);
+                    if (a.recheck && __builtin_amdgcn_ballot_w64(closest < band) != 0) queue(std::false_type{});
+                }
+            } else {
             // Columns past the tile (ok false) are skipped: with TY * L/2 not a
             // multiple of the block size whole wavefronts have nothing to do
             // in the last column, and the branch lets them skip it.
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
-                if (!ok[s]) continue;
+                if (!FULL && !ok[s]) continue;
                 const f2 n1 = bc[lc[s] - half];
                 const f2 n2 = bc[lc[s] + half];
                 const f2 n3 = bc[lc[s]];
@@ -432,10 +568,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 if constexpr (KIND == kOver) {
                     nv = overrelax_turns(cur[s], hx, hy);
                 } else if constexpr (KIND == kMetro) {
-                    // one Philox block per pair of planes (2m, 2m+1) of this
-                    // column: drawn at the even plane (or at the tile's first
-                    // plane when that is odd), its last two words kept for
-                    // the odd plane
                     uint32_t w0, w1;
                     if ((z & 1) == 0 || zz == 0) {
                         const int zb = z & ~1;
@@ -458,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                     const f2 so = sincos_turns(cur[s]);
                     const f2 sn = sincos_turns(prop);
                     const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
-                    const float pa = __expf(-beta * dE);
+                    const float pa = __builtin_amdgcn_exp2f(dE * nbl2e);
                     const bool acc = u1 < pa;
                     if (a.recheck && __builtin_fabsf(u1 - pa) < band) {
                         const uint32_t idx = atomicAdd(&a.rq->count, 1u);
@@ -466,19 +598,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                             RecheckEntry e;
                             e.li = li;
                             e.slot = slot;
-                            e.q = (int32_t)((sz + voff[s]) >> 2);
+                            e.q = ((sz + voff[s]) >> 2) | ((acc ? 1u : 0u) << 31);
                             e.cur = cur[s];
-                            e.prop = prop;
-                            e.u1 = u1;
-                            e.fp32_accept = acc ? 1 : 0;
-                            e.pad_ = 0;
                             a.rq->entries[idx] = e;
                         } else {
                             atomicAdd(&a.rq->overflow, 1u);
                         }
                     }
                     nv = acc ? prop : cur[s];
-                    nacc += acc ? 1ull : 0ull;
+                    nacc_w += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(acc));
                 }
                 if constexpr (MEAS || KIND == kMeas) {
                     const f2 sc = sincos_turns(nv);
@@ -492,11 +620,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
                 }
                 if constexpr (KIND != kMeas) bstore(nv, rown, voff[s], sz);
             }
+            }
 
             // Plane z+1 into the other LDS buffer; plane z+2 into registers.
 #pragma unroll
             for (int s = 0; s < SPT; ++s) {
-                if (!ok[s]) continue;
+                if (!FULL && !ok[s]) continue;
                 bn[lc[s]] = ocp[s];
                 ocp[s] = sincos_turns(pre_o[s]);
                 cur[s] = pre_c[s];
@@ -512,7 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_f32(SweepArgs a)
             if (zz + 1 < d.TZ) step(zz + 1, buf1, buf0, lx_odd, b_o, b_c, b_h, a_o, a_c, a_h);
         }
 
-        if constexpr (KIND == kMetro) block_add_accepts(nacc, a.macc + d.pos_base + k);
+        if constexpr (KIND == kMetro)
+            block_add_accepts((threadIdx.x & 63) == 0 ? (unsigned long long)nacc_w : 0ull, a.macc + d.pos_base + k);
         if constexpr (MEAS || KIND == kMeas)
             block_store_partials(acc, a.partials + kPartials * (int64_t)w, a.bonds ? kPartials : kPartialsNoBonds);
     }
@@ -554,7 +684,14 @@ enum Or2Measure : int { kOr2Plain = 0, kOr2Measure = 1, kOr2MeasureBonds = 2 };
 
 constexpr int or2_min_waves(int meas, int spt) { return (meas == kOr2Measure && spt <= 3) ? 4 : 1; }
 
-template <int MEAS, int SPT>
+// Elements of one old-colour-1 plane buffer of the fused kernel: a bound on
+// (TY + 4) * L/2 (TY * L/2 <= SPT * kBlock tile sites, L/2 <= kBlock/2).
+template <int SPT>
+constexpr int kOr2P1Elems = SPT * kBlock + 2 * kBlock;
+
+// LEAD: every lattice of the launch fills the tile's first SPT - 1 columns
+// (TY * L/2 > (SPT - 1) * kBlock), so only the last column needs a guard.
+template <int MEAS, int SPT, bool LEAD>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(or2_min_waves(MEAS, SPT))))
 void k_or2_f32(SweepArgs a)
 {
@@ -581,9 +718,12 @@ void k_or2_f32(SweepArgs a)
         const __amdgpu_buffer_rsrc_t r0d = colour_rsrc(dst, nh);
         const __amdgpu_buffer_rsrc_t r1d = colour_rsrc(dst + nh, nh);
         const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(src, 0);
-        const int rows1 = TY + 4, rows0 = TY + 2;
-        f2 *P1[2] = {lds, lds + rows1 * half};
-        f2 *P0base = lds + 2 * rows1 * half;
+        // P1 buffers at compile-time offsets (the alternating steps address
+        // them through immediate LDS offsets); the three rotating P0 buffers
+        // after them
+        const int rows0 = TY + 2;
+        f2 *P1[2] = {lds, lds + kOr2P1Elems<SPT>};
+        f2 *P0base = lds + 2 * kOr2P1Elems<SPT>;
         auto P0 = [&](int b) { return P0base + b * rows0 * half; };
         auto wrapy = [L](int y) { return y < 0 ? y + L : (y >= L ? y - L : y); };
         auto wrapz = wrapy;
@@ -604,7 +744,7 @@ void k_or2_f32(SweepArgs a)
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
             const int f = tid + s * kBlock;
-            okT[s] = f < TY * half;
+            okT[s] = (LEAD && s < SPT - 1) || f < TY * half;
             const int fl = okT[s] ? f : 0;
             const int yl = fl / half, j = fl - yl * half, y = y0 + yl;
             voffT[s] = (uint32_t)(y * half + j) * 4u;
@@ -1048,65 +1188,76 @@ static hipError_t launch_or_query(SweepKernel k, int grid, size_t lds, const Swe
     return hipGetLastError();
 }
 
-template <int KIND, bool MEAS, int HALO>
+template <int KIND, bool MEAS, int HALO, bool FULL>
 static hipError_t launch_tile_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
                                   int *per_cu)
 {
     switch (spt) {
-    case 1: return launch_or_query(k_tile_f32<KIND, MEAS, 1, HALO>, grid, lds, a, s, per_cu);
-    case 2: return launch_or_query(k_tile_f32<KIND, MEAS, 2, HALO>, grid, lds, a, s, per_cu);
-    case 3: return launch_or_query(k_tile_f32<KIND, MEAS, 3, HALO>, grid, lds, a, s, per_cu);
-    case 4: return launch_or_query(k_tile_f32<KIND, MEAS, 4, HALO>, grid, lds, a, s, per_cu);
-    case 5: return launch_or_query(k_tile_f32<KIND, MEAS, 5, HALO>, grid, lds, a, s, per_cu);
-    case 6: return launch_or_query(k_tile_f32<KIND, MEAS, 6, HALO>, grid, lds, a, s, per_cu);
-    case 8: return launch_or_query(k_tile_f32<KIND, MEAS, 8, HALO>, grid, lds, a, s, per_cu);
+    case 1: return launch_or_query(k_tile_f32<KIND, MEAS, 1, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 2: return launch_or_query(k_tile_f32<KIND, MEAS, 2, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 3: return launch_or_query(k_tile_f32<KIND, MEAS, 3, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 4: return launch_or_query(k_tile_f32<KIND, MEAS, 4, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 5: return launch_or_query(k_tile_f32<KIND, MEAS, 5, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 6: return launch_or_query(k_tile_f32<KIND, MEAS, 6, HALO, FULL>, grid, lds, a, s, per_cu);
+    case 8: return launch_or_query(k_tile_f32<KIND, MEAS, 8, HALO, FULL>, grid, lds, a, s, per_cu);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int HALO>
-static hipError_t launch_tile_halo(int kind, bool fuse_measure, int spt, int grid, size_t lds,
+static hipError_t launch_tile_halo(int kind, bool fuse_measure, bool full, int spt, int grid, size_t lds,
                                    const SweepArgs &a, hipStream_t s, int *per_cu)
 {
+    // the unguarded (FULL) variant exists for the plain Metropolis half-sweep
+    if (kind == kMetro && !fuse_measure && full)
+        return launch_tile_spt<kMetro, false, HALO, true>(spt, grid, lds, a, s, per_cu);
     if (kind == kMetro)
-        return fuse_measure ? launch_tile_spt<kMetro, true, HALO>(spt, grid, lds, a, s, per_cu)
-                            : launch_tile_spt<kMetro, false, HALO>(spt, grid, lds, a, s, per_cu);
+        return fuse_measure ? launch_tile_spt<kMetro, true, HALO, false>(spt, grid, lds, a, s, per_cu)
+                            : launch_tile_spt<kMetro, false, HALO, false>(spt, grid, lds, a, s, per_cu);
     if (kind == kOver)
-        return fuse_measure ? launch_tile_spt<kOver, true, HALO>(spt, grid, lds, a, s, per_cu)
-                            : launch_tile_spt<kOver, false, HALO>(spt, grid, lds, a, s, per_cu);
-    return launch_tile_spt<kMeas, false, HALO>(spt, grid, lds, a, s, per_cu);
+        return fuse_measure ? launch_tile_spt<kOver, true, HALO, false>(spt, grid, lds, a, s, per_cu)
+                            : launch_tile_spt<kOver, false, HALO, false>(spt, grid, lds, a, s, per_cu);
+    return launch_tile_spt<kMeas, false, HALO, false>(spt, grid, lds, a, s, per_cu);
 }
 
-hipError_t launch_tile_f32(int kind, bool fuse_measure, int spt, int halo, int grid, size_t lds,
+hipError_t launch_tile_f32(int kind, bool fuse_measure, bool full, int spt, int halo, int grid, size_t lds,
                            const SweepArgs &a, hipStream_t s, int *per_cu)
 {
-    if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, spt, grid, lds, a, s, per_cu);
-    if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, spt, grid, lds, a, s, per_cu);
+    if (halo == 1) return launch_tile_halo<1>(kind, fuse_measure, full, spt, grid, lds, a, s, per_cu);
+    if (halo == 4) return launch_tile_halo<4>(kind, fuse_measure, full, spt, grid, lds, a, s, per_cu);
     return hipErrorInvalidValue;
 }
 
-template <int MEAS>
+template <int MEAS, bool LEAD>
 static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
                                  int *per_cu)
 {
     switch (spt) {
-    case 1: return launch_or_query(k_or2_f32<MEAS, 1>, grid, lds, a, s, per_cu);
-    case 2: return launch_or_query(k_or2_f32<MEAS, 2>, grid, lds, a, s, per_cu);
-    case 3: return launch_or_query(k_or2_f32<MEAS, 3>, grid, lds, a, s, per_cu);
-    case 4: return launch_or_query(k_or2_f32<MEAS, 4>, grid, lds, a, s, per_cu);
-    case 5: return launch_or_query(k_or2_f32<MEAS, 5>, grid, lds, a, s, per_cu);
-    case 6: return launch_or_query(k_or2_f32<MEAS, 6>, grid, lds, a, s, per_cu);
-    case 8: return launch_or_query(k_or2_f32<MEAS, 8>, grid, lds, a, s, per_cu);
+    case 1: return launch_or_query(k_or2_f32<MEAS, 1, LEAD>, grid, lds, a, s, per_cu);
+    case 2: return launch_or_query(k_or2_f32<MEAS, 2, LEAD>, grid, lds, a, s, per_cu);
+    case 3: return launch_or_query(k_or2_f32<MEAS, 3, LEAD>, grid, lds, a, s, per_cu);
+    case 4: return launch_or_query(k_or2_f32<MEAS, 4, LEAD>, grid, lds, a, s, per_cu);
+    case 5: return launch_or_query(k_or2_f32<MEAS, 5, LEAD>, grid, lds, a, s, per_cu);
+    case 6: return launch_or_query(k_or2_f32<MEAS, 6, LEAD>, grid, lds, a, s, per_cu);
+    case 8: return launch_or_query(k_or2_f32<MEAS, 8, LEAD>, grid, lds, a, s, per_cu);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_or2_f32(bool fuse_measure, int spt, int grid, size_t lds, const SweepArgs &a,
+template <int MEAS>
+static hipError_t launch_or2_lead(bool lead, int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
+                                  int *per_cu)
+{
+    return lead ? launch_or2_spt<MEAS, true>(spt, grid, lds, a, s, per_cu)
+                : launch_or2_spt<MEAS, false>(spt, grid, lds, a, s, per_cu);
+}
+
+hipError_t launch_or2_f32(bool fuse_measure, bool lead, int spt, int grid, size_t lds, const SweepArgs &a,
                           hipStream_t s, int *per_cu)
 {
-    if (!fuse_measure) return launch_or2_spt<kOr2Plain>(spt, grid, lds, a, s, per_cu);
-    return a.bonds ? launch_or2_spt<kOr2MeasureBonds>(spt, grid, lds, a, s, per_cu)
-                   : launch_or2_spt<kOr2Measure>(spt, grid, lds, a, s, per_cu);
+    if (!fuse_measure) return launch_or2_lead<kOr2Plain>(lead, spt, grid, lds, a, s, per_cu);
+    return a.bonds ? launch_or2_lead<kOr2MeasureBonds>(lead, spt, grid, lds, a, s, per_cu)
+                   : launch_or2_lead<kOr2Measure>(lead, spt, grid, lds, a, s, per_cu);
 }
 
 hipError_t launch_recheck(const SweepArgs &a, hipStream_t s)
