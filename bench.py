@@ -33,6 +33,8 @@ METRIC = "spin updates/sec at L=160×32 replicas; % HBM roofline; FP32 vs FP64 a
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE_F32 = 12.0   # a half-sweep reads N angles, writes N/2: 6N B per N/2 updates
 BYTES_PER_UPDATE_F64 = 24.0
+FUSED_MIN_BYTES_PER_UPDATE = 8.0  # one pass over both colours: read 4 B and write 4 B per site
+SINCOS_AMPLITUDE_DEFICIT = 3.3e-8  # mean 1 - |(cos, sin)| of the hardware sine/cosine (measured on gfx950)
 
 L, R, SEED = 160, 32, 4
 BETA_LO, BETA_HI = 0.4538, 0.4546
@@ -54,11 +56,43 @@ def _oracle_one_sweep(args):
     return (N_METRO + N_OR) * L_ ** 3, dt
 
 
+def _oracle_run(args):
+    """A whole oracle run (sweeps, measurement every sweep, exchange as given)
+    on one core; returns (site-updates, seconds)."""
+    L_, betas, seed, n, n_metro, n_or, every = args
+    import numpy as np
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.run(L_, np.array(betas), seed, n, n_metro, n_or, exchange_every=every)
+    dt = time.perf_counter() - t0
+    return (n_metro + n_or) * L_ ** 3 * len(betas) * n, dt
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(window=0.0):
+    """The oracle on the host: all available cores on one sweep of L = 160
+    configurations (one process per configuration), then single-core runs of
+    the two small workloads (the L = 8 single-lattice chain in full, and 100
+    sweeps of the L = 32 tempering ladder)."""
     import numpy as np
     import oracle
     oracle.build()
-    cores = max(1, min(16, os.cpu_count() or 1, R))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, R))
     betas = np.linspace(BETA_LO, BETA_HI, R)
     jobs = [(k, L, float(betas[k]), SEED, window) for k in range(cores)]
     t0 = time.perf_counter()
@@ -74,16 +108,31 @@ def cpu_baseline(window=0.0):
     wall = time.perf_counter() - t0
     updates = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
+    # single core: each run alone in its own process, the two side by side
+    singles = [("L=8 single lattice, beta 0.4542, 1 + 1, 10^4 sweeps, measurement every sweep (in full)",
+                (8, [0.4542], 1, 10000, 1, 1, 0)),
+               ("L=32 ladder, 16 replicas over [0.450, 0.458], 1 + 5, exchange every sweep, 100 sweeps",
+                (32, list(np.linspace(0.450, 0.458, 16)), 2, 100, 1, 5, 1))]
+    pool = mp.get_context("spawn").Pool(len(singles))
+    try:
+        sres = pool.map(_oracle_run, [a for _, a in singles])
+    finally:
+        pool.close()
+        pool.join()
+    single_core = [{"workload": name, "site_updates": u, "seconds": round(t, 2),
+                    "ns_per_update": round(1e9 * t / u, 1)} for (name, _), (u, t) in zip(singles, sres)]
     return {
         "value": updates / busy,
         "unit": "site-updates/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"{cores} configurations of L={L} (one per process), one sweep of "
-                  f"{N_METRO} Metropolis + {N_OR} over-relaxation each, beta in "
+        "sample": f"{cores} configurations of L={L} (one process each, one per available core), one "
+                  f"sweep of {N_METRO} Metropolis + {N_OR} over-relaxation each, beta in "
                   f"[{BETA_LO}, {BETA_HI}], {proposal_text(window)}; rate over the slowest "
                   "process's sweep time "
                   f"({busy:.1f} s; wall {wall:.1f} s incl. start-up)",
+        "host": {"nproc": os.cpu_count(), "cores_available": avail, "cpu_model": cpu_model()},
+        "single_core": single_core,
     }
 
 
@@ -101,9 +150,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_FILES = {
+    "fused": "traffic_fused_over_relax_L160x32.json",
+    "half": "traffic_over_relax_L160x32.json",
+    "metro": "traffic_metropolis_L160x32.json",
+}
+
+
 def traffic_path(kind):
-    name = "traffic_fused_over_relax_L160x32.json" if kind == "fused" else "traffic_over_relax_L160x32.json"
-    return os.path.join(ROOT, "profiles", name)
+    return os.path.join(ROOT, "profiles", TRAFFIC_FILES[kind])
 
 
 def load_traffic(kernel_hash, kind):
@@ -156,28 +211,32 @@ def _pmc_rows(path, counter):
 
 
 def digest_traffic(fetch_csv, write_csv):
-    """Scale the over-relaxation kernel's FETCH_SIZE / WRITE_SIZE by what the
-    same counters read for the plain copy of COPY_BYTES, and store the HBM
-    bytes per launch together with the kernel source hash."""
+    """Scale the profiled kernel's FETCH_SIZE / WRITE_SIZE (the fused
+    over-relaxation substep, the over-relaxation half-sweep, or the
+    Metropolis half-sweep, whichever the probe ran) by what the same counters
+    read for the plain copy of COPY_BYTES, and store the HBM bytes per launch
+    together with the kernel source hash."""
     out = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _pmc_rows(path, counter)
         copy = [v for n, v in rows if "elementwise" in n or "copy" in n.lower()]
-        fused = [v for n, v in rows if "k_or2_f32" in n]
-        half = [v for n, v in rows if "k_tile_f32<1," in n]
-        over = fused or half
-        kind = "fused" if fused else "half"
-        if not copy or not over:
-            raise SystemExit(f"{path}: copy or over-relaxation dispatches not found")
+        found = {"fused": [v for n, v in rows if "k_or2_f32" in n],
+                 "half": [v for n, v in rows if "k_tile_f32<1," in n],
+                 "metro": [v for n, v in rows if "k_tile_f32<0," in n]}
+        kind = next((k for k in ("fused", "half", "metro") if found[k]), None)
+        if not copy or kind is None:
+            raise SystemExit(f"{path}: copy or profiled-kernel dispatches not found")
+        vals = found[kind]
         scale = COPY_BYTES / max(copy)
-        out[f"{key}_counter_per_launch"] = sum(over) / len(over)
+        out[f"{key}_counter_per_launch"] = sum(vals) / len(vals)
         out[f"{key}_copy_counter"] = max(copy)
         out[f"{key}_scale_bytes_per_unit"] = scale
         out[f"{key}_bytes_per_launch"] = out[f"{key}_counter_per_launch"] * scale
     out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
     out["kernel"] = kind
     out["algorithmic_bytes_per_launch"] = BYTES_PER_UPDATE_F32 * R * L ** 3 / (1 if kind == "fused" else 2)
-    probe = "python3 bench.py --traffic-probe" + ("" if kind == "fused" else " --unfused")
+    probe = {"fused": "python3 bench.py --traffic-probe", "half": "python3 bench.py --traffic-probe --unfused",
+             "metro": "python3 bench.py --metro-probe"}[kind]
     out["commands"] = [
         f"rocprofv3 --pmc {c} -d <dir> -o run --output-format csv -- {probe}"
         for c in ("FETCH_SIZE", "WRITE_SIZE")
@@ -313,6 +372,32 @@ def main():
         "avg_launch_ms_by_kernel": {k: (round(v, 4) if v is not None else None) for k, v in avg.items()},
         "kernel_source_hash": khash,
     }
+    if cnt["over_fused"]:
+        # the fused pass reads both colours once and writes both once: its own
+        # minimum is 8 B per site-update (16 B per site per launch), so against
+        # that the same launch time is a lower fraction
+        own_min = FUSED_MIN_BYTES_PER_UPDATE * R * N
+        roofline["own_min_bytes_per_update"] = FUSED_MIN_BYTES_PER_UPDATE
+        roofline["frac_own_min"] = round(own_min / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    if traffic:
+        # HBM bytes the counters saw per launch (an upper bound: L2 misses,
+        # some of which the Infinity Cache may serve), over the launch time
+        roofline["measured_gbs"] = round(traffic / (kms / 1e3) / 1e9, 1)
+        roofline["measured_frac"] = round(traffic / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    if cnt["metro"]:
+        # the Metropolis half-sweep (one launch per colour; its float64
+        # re-decision launch included in the time): 12 B per site-update
+        mms = avg["metro"]
+        mbytes = BYTES_PER_UPDATE_F32 * R * N / 2
+        mtraffic = load_traffic(khash, "metro")
+        roofline["metropolis"] = {
+            "avg_launch_ms": round(mms, 4),
+            "algorithmic_bytes_per_launch": mbytes,
+            "achieved": round(mbytes / (mms / 1e3) / 1e9, 1),
+            "frac": round(mbytes / (mms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": mtraffic,
+            "measured_gbs": round(mtraffic / (mms / 1e3) / 1e9, 1) if mtraffic else None,
+        }
     # FP32 against FP64 on the same configurations: the state the timed run
     # left in two replicas, measured by the FP32 kernels and by the FP64
     # kernels of a one-replica FP64 context holding the same angles
@@ -323,17 +408,22 @@ def main():
         s64.set_angles(sim.get_angles(0, k))
         o64 = s64.measure()[0]
         s64.close()
-        errs.append((abs(obs32[k, 1] - o64[1]), abs(obs32[k, 2] - o64[2]), abs(obs32[k, 0] - o64[0])))
+        errs.append((abs(obs32[k, 1] - o64[1]), abs(obs32[k, 2] - o64[2]), abs(obs32[k, 0] - o64[0]),
+                     abs(o64[1])))
     fp32_vs_fp64 = {
         "replicas": [0, R - 1],
         "max_abs_err_e": float(max(e[0] for e in errs)),
         "max_abs_err_abs_m": float(max(e[1] for e in errs)),
         "max_abs_err_E": float(max(e[2] for e in errs)),
-        "tolerance_e": 1e-6,
+        # the hardware sine/cosine return unit vectors 3.3e-8 short on average,
+        # which scales every float32 bond term by 1 - 6.5e-8: bound at twice that
+        "tolerance_e": 2 * 2 * SINCOS_AMPLITUDE_DEFICIT * float(max(e[3] for e in errs)),
         "tolerance_abs_m": 1e-6,
         "note": "observables of the same configurations from the float32 path (float64 "
-                "accumulation) and from the float64 kernels; per-sweep angle parity with the "
-                "float64 oracle is 2e-5 rad (float32) and 1e-12 rad (float64), checked by the tests",
+                "accumulation) and from the float64 kernels; the energy error is the relative "
+                "bias 2 x 3.3e-8 of the hardware sine/cosine amplitude (measured); per-sweep "
+                "angle parity with the float64 oracle is 2e-5 rad (float32) and 1e-12 rad "
+                "(float64), checked by the tests",
     }
     sim.close()
     del obs

@@ -315,16 +315,25 @@ xy_status xy_set_tiling(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz, int
  * of one Metropolis and one over-relaxation half-sweep (n_unfused: the
  * over-relaxation substeps that do not run fused), then, when n_or >= 2 and
  * the context fuses over-relaxation, the fused tiles, cost = one fused
- * substep.  Each timing is reps launches after one warm-up launch.  The
- * angles and acceptance counters are saved and restored around the timing,
- * so the chain is unchanged.  Needs scratch device memory the size of the
- * angle buffer.  No-op for FP64 contexts.  Waits.
+ * substep.  Then the sublattice schedule of the over-relaxation substeps:
+ * the fused pass (both colours per launch) or two half-sweep launches, the
+ * faster kept (bit-identical results either way); then the workgroup cap of
+ * the tiled launches among the resident capacity and 2, 3, 4, 6 workgroups
+ * per compute unit, cost = one whole sweep.  Each timing is reps launches
+ * after one warm-up launch.  The angles and acceptance counters are saved
+ * and restored around the timing and the sweep counter is not advanced, so
+ * the chain is unchanged.  Needs scratch device memory the size of the angle
+ * buffer.  No-op for FP64 contexts.  Waits.
  */
 xy_status xy_autotune(xy_ctx ctx, int32_t n_metro, int32_t n_or, int32_t reps);
 xy_status xy_get_tiling(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz, int32_t *grid_cap);
 
 /* The same for the fused over-relaxation kernel (its own tiles; rows and
- * planes as above).  XY_ERR_UNSUPPORTED when the context does not fuse. */
+ * planes as above; ty * L/2 <= 1280).  Setting a fused tile also selects the
+ * fused schedule (which xy_autotune may have switched off).
+ * XY_ERR_UNSUPPORTED when the context cannot fuse (FP64, XY_F_NO_FUSED_OR,
+ * or a lattice with L > 256); xy_get_tiling_fused reports (0, 0) while the
+ * fused schedule is not in use. */
 xy_status xy_set_tiling_fused(xy_ctx ctx, int32_t lattice, int32_t ty, int32_t tz);
 xy_status xy_get_tiling_fused(xy_ctx ctx, int32_t lattice, int32_t *ty, int32_t *tz);
 

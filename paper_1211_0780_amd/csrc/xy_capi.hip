@@ -147,7 +147,8 @@ struct xy_ctx_s {
     std::vector<GraphEntry> graphs;
     std::vector<Tiling> tiles;  // FP32: per-lattice tile choice of the half-sweep kernels
     std::vector<Tiling> tiles2; // FP32: per-lattice tile choice of the fused over-relaxation
-    bool fused_or = false;      // over-relaxation substeps as one fused kernel each
+    bool fused_avail = false;   // the fused kernel's layout and second buffer exist (FP32, every L <= kBlock)
+    bool fused_or = false;      // over-relaxation substeps run as one fused kernel each (the schedule in use)
     double window = 0.0;        // Metropolis proposal window (radians, 0: uniform)
     std::vector<LatDev> lat_or2;
     int items_or2 = 0, spt2 = 0;
@@ -599,7 +600,7 @@ void build_layout(xy_ctx c)
     c->items_or2 = 0;
     c->spt2 = 1;
     c->lds2 = 0;
-    if (c->fused_or) {
+    if (c->fused_avail) {
         int item2 = 0;
         size_t p0_elems = 0;
         for (int l = 0; l < c->n_lat; ++l) {
@@ -646,7 +647,7 @@ xy_status relayout(xy_ctx c)
                              hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipMemcpyAsync(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat,
                              hipMemcpyHostToDevice, c->stream));
-    if (c->fused_or)
+    if (c->fused_avail)
         XY_HIP(c, hipMemcpyAsync(c->d_lat_or2, c->lat_or2.data(), sizeof(LatDev) * c->n_lat,
                                  hipMemcpyHostToDevice, c->stream));
     XY_HIP(c, hipStreamSynchronize(c->stream));
@@ -729,9 +730,10 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     c->elem = (c->prec == XY_FP32) ? 4 : 8;
     c->n_elems = total_elems(cfg);
     c->stream = (hipStream_t)cfg->stream;
-    c->fused_or = c->prec == XY_FP32 && !(cfg->flags & XY_F_NO_FUSED_OR);
+    c->fused_avail = c->prec == XY_FP32 && !(cfg->flags & XY_F_NO_FUSED_OR);
     for (int l = 0; l < c->n_lat; ++l)
-        if (c->L[l] > kBlock) c->fused_or = false;
+        if (c->L[l] > kBlock) c->fused_avail = false;
+    c->fused_or = c->fused_avail;
     build_layout(c);
 
     auto bail = [&](xy_status s) {
@@ -767,7 +769,7 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
         c->own_ang = true;
     }
     const int n_items_max = std::max(std::max(c->items_sweep, c->items_meas), c->items_or2);
-    if (c->fused_or) {
+    if (c->fused_avail) {
         if ((st = dev_alloc(c, (char **)&c->ang2, (size_t)c->n_elems * c->elem)) ||
             (st = dev_alloc(c, &c->d_lat_or2, c->n_lat)))
             return bail(st);
@@ -810,7 +812,7 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c->d_lat_sweep, c->lat_sweep.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_lat_meas, c->lat_meas.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
-    if (e == hipSuccess && c->fused_or)
+    if (e == hipSuccess && c->fused_avail)
         e = hipMemcpy(c->d_lat_or2, c->lat_or2.data(), sizeof(LatDev) * c->n_lat, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_beta, c->beta.data(), sizeof(double) * c->R_total, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_pos, ident.data(), sizeof(int32_t) * c->R_total, hipMemcpyHostToDevice);
@@ -1059,12 +1061,14 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: for each lattice, time one Metropolis and one over-relaxation
-// half-sweep of that lattice alone for every admissible (ty, tz), weight them
-// by the sweep composition, keep the fastest.  The lattice's angles and
-// acceptance counters are saved before and restored after, and the
-// near-threshold re-decision is off while timing, so tuning leaves the chain
-// untouched.
+// Autotuner: tiles of each lattice for the Metropolis and over-relaxation
+// half-sweeps and for the fused substep, timed on the whole batch
+// (coordinate descent over the lattices), then the over-relaxation schedule
+// (fused pass or two half-sweeps) and the workgroup cap.  The Metropolis
+// launches are timed with their float64 re-decision, as they run in a sweep.
+// Angles and acceptance counters are saved before and restored after, and
+// the sweep counter is not advanced, so tuning leaves the chain untouched
+// (tiles, schedule and cap change the launches, not the result).
 // ---------------------------------------------------------------------------
 xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
 {
@@ -1126,7 +1130,8 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
         c->tiles[l] = best;
         st = relayout(c);
     }
-    if (!st && c->fused_or && n_or >= 2) {
+    if (!st && c->fused_avail && n_or >= 2) {
+        c->fused_or = true;
         for (int l = 0; l < c->n_lat && !st; ++l) {
             Tiling best = c->tiles2[l];
             double best_ms = 1e300;
@@ -1145,6 +1150,41 @@ xy_status xy_autotune(xy_ctx c, int32_t n_metro, int32_t n_or, int32_t reps)
             c->tiles2[l] = best;
             st = relayout(c);
         }
+    }
+    // Sublattice schedule of the over-relaxation substeps: one fused pass
+    // over both colours, or the two half-sweep launches (the same result, bit
+    // for bit); the faster in the tiles just chosen is kept.
+    if (!st && c->fused_avail && n_or >= 2) {
+        double ms_fused = 0.0, ms_half = 0.0;
+        st = time_launches(c, e0, e1, reps, [&] { return launch_or2(c, c->ang, c->ang2, false); }, &ms_fused);
+        if (!st)
+            st = time_launches(c, e0, e1, reps, [&] {
+                const xy_status s0 = launch_half(c, kOver, 0, 0, false);
+                return s0 ? s0 : launch_half(c, kOver, 1, 0, false);
+            }, &ms_half);
+        if (!st) {
+            c->fused_or = ms_fused <= ms_half;
+            st = relayout(c);
+        }
+    }
+    // Workgroup cap of the tiled and fused launches: the resident capacity
+    // (0) or a fixed multiple of the compute units, timed on whole sweeps
+    // (the sweep counter is not advanced; the state is restored below).
+    if (!st) {
+        int best_cap = c->grid_sweep;
+        double best_ms = 1e300;
+        for (const int cap : {0, 2 * c->n_cu, 3 * c->n_cu, 4 * c->n_cu, 6 * c->n_cu}) {
+            c->grid_sweep = cap;
+            double ms = 0.0;
+            if ((st = time_launches(c, e0, e1, reps, [&] { return enqueue_sweep(c, n_metro, n_or, false, false, false); },
+                                    &ms)))
+                break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_cap = cap;
+            }
+        }
+        c->grid_sweep = best_cap;
     }
     (void)hipStreamSynchronize(c->stream);
     if (hipMemcpyAsync(c->ang, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
@@ -1194,7 +1234,7 @@ xy_status xy_set_proposal_window(xy_ctx c, double window)
 xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
-    if (!c->fused_or) return fail(c, XY_ERR_UNSUPPORTED, "this context does not use the fused over-relaxation");
+    if (!c->fused_avail) return fail(c, XY_ERR_UNSUPPORTED, "this context cannot use the fused over-relaxation");
     if (lattice < 0 || lattice >= c->n_lat) return fail(c, XY_ERR_ARG, "lattice out of range");
     const int L = c->L[lattice];
     if (ty < 1 || tz < 1 || L % ty != 0 || L % tz != 0)
@@ -1206,6 +1246,7 @@ xy_status xy_set_tiling_fused(xy_ctx c, int32_t lattice, int32_t ty, int32_t tz)
     t.TZ = tz;
     t.spt = spt_for(ty * (L / 2));
     c->tiles2[lattice] = t;
+    c->fused_or = true;  // a fused tile selects the fused schedule
     return relayout(c);
 }
 

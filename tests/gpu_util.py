@@ -70,3 +70,16 @@ def check_or_substep(start, got, L, fp64=False):
         worst = max(worst, float(r[mask].max()))
         base = np.where(m0, got, base) if colour == 0 else base
     return worst
+
+
+# Measured on gfx950 over x = i / 2^24: the hardware sine and cosine of an
+# angle in turns return unit vectors that are short by 3.23e-8 on average
+# (the polynomial alternative: 5e-9), so every float32 bond term
+# S_i . S_j = |S_i| |S_j| cos(theta_i - theta_j) is scaled by about
+# 1 - 6.5e-8 and the float32 energy carries that relative bias.  Bound: twice
+# the bias on |E|, plus the random rounding of N/2 float32 terms of size <= 6.
+AMPLITUDE_DEFICIT = 3.3e-8
+
+
+def e_tol_fp32(E_ref, N):
+    return 2 * (2 * AMPLITUDE_DEFICIT) * abs(E_ref) + 4 * 6 * 2.0 ** -24 * np.sqrt(N)

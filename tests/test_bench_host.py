@@ -28,8 +28,9 @@ def _counter_csv(path, counter, rows):
             w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
 
 
-@pytest.mark.parametrize("kind,kernel", [("fused", "void xy::k_or2_f32<0, 3>(xy::SweepArgs)"),
-                                         ("half", "void xy::k_tile_f32<1, false, 3, 1>(xy::SweepArgs)")])
+@pytest.mark.parametrize("kind,kernel", [("fused", "void xy::k_or2_f32<0, 3, true>(xy::SweepArgs)"),
+                                         ("half", "void xy::k_tile_f32<1, false, 3, 1, false>(xy::SweepArgs)"),
+                                         ("metro", "void xy::k_tile_f32<0, false, 5, 1, true>(xy::SweepArgs)")])
 def test_traffic_digest_scales_by_the_copy(tmp_path, monkeypatch, kind, kernel):
     out = tmp_path / f"traffic_{kind}.json"
     monkeypatch.setattr(bench, "traffic_path", lambda k: str(out))
@@ -62,3 +63,11 @@ def test_traffic_digest_rejects_files_without_the_copy(tmp_path, monkeypatch):
     _counter_csv(write, "WRITE_SIZE", [(kernel, 3.0)])
     with pytest.raises(SystemExit):
         bench.digest_traffic(str(fetch), str(write))
+
+
+def test_cpu_model_and_oracle_run_timing():
+    """The host description and the single-core timing helper of the CPU
+    baseline (a tiny oracle run)."""
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+    updates, secs = bench._oracle_run((4, [0.3, 0.4], 3, 2, 1, 1, 1))
+    assert updates == 2 * 4 ** 3 * 2 * 2 and secs > 0

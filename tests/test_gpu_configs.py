@@ -25,7 +25,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import check_metro_half, check_or_substep, colour_mask, gpu_states
+from gpu_util import check_metro_half, check_or_substep, colour_mask, e_tol_fp32, gpu_states
 from stats_util import binder, bins_mean, bins_ratio, bonferroni_z, chain_bins, z_family
 
 pytestmark = pytest.mark.gpu
@@ -119,7 +119,7 @@ def test_ladder_measuring_fused_substep(ladder):
         check_or_substep(before[k], mid, L_PT)
         check_or_substep(mid, after, L_PT)
         ref = oracle.measure(after, L_PT)
-        assert abs(o[k, 0] - ref[0]) <= 2e-7 * N, (k, o[k, 0], ref[0])
+        assert abs(o[k, 0] - ref[0]) <= e_tol_fp32(ref[0], N), (k, o[k, 0], ref[0])
         assert abs(o[k, 2] - ref[2]) <= 1e-6
 
 
@@ -178,12 +178,19 @@ def test_ladder_long_run_matches_oracle_statistics(gpu):
     s.close()
 
 
+# fused tiles of the batch, one per lattice (an earlier autotuner pick); set
+# explicitly so that the fused pass runs whichever schedule the tuner prefers
+FSS_FUSED_TILES = [(24, 24), (32, 32), (24, 24), (16, 32), (16, 24), (8, 32)]
+
+
 @pytest.fixture(scope="module")
 def fss(gpu):
     s = make(FSS_LS, [BETAS_FSS] * len(FSS_LS), SEED_FSS)
     s.autotune(1, 10, reps=1)
-    for l in range(len(FSS_LS)):
-        assert s.get_tiling_fused(l) != (0, 0)
+    print(f"[fss] autotuned: half-sweep tiles {[s.get_tiling(l) for l in range(len(FSS_LS))]}, "
+          f"fused tiles {[s.get_tiling_fused(l) for l in range(len(FSS_LS))]} ((0, 0): two half-sweeps)")
+    for l, (ty, tz) in enumerate(FSS_FUSED_TILES):
+        s.set_tiling_fused(l, ty, tz)
     s.run(2, 1, 10, exchange_every=1)
     yield s
     s.close()
