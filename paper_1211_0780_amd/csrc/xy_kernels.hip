@@ -756,8 +756,12 @@ void k_or2_f32(SweepArgs a)
         }
         auto l1T = [&](int s) { return (int)(voffT[s] >> 2) + sh1; };
         auto l0T = [&](int s) { return (int)(voffT[s] >> 2) + sh0; };
-        const bool okH = tid < 2 * half;
-        const int eH = okH ? tid : 0;
+        // halo rows on the last 2 * L/2 threads: the last tile column is
+        // populated from the first thread on, so the halo goes to the
+        // wavefronts that have fewer tile columns
+        const int hbase = kBlock - 2 * half;
+        const bool okH = tid >= hbase;
+        const int eH = okH ? tid - hbase : 0;
         const int rH = eH >= half, jH = eH - rH * half;
         const int yH = rH ? wrapy(y0 + TY) : wrapy(y0 - 1);
         const uint32_t voffH = (uint32_t)(yH * half + jH) * 4u;

@@ -44,7 +44,8 @@ def run_batch(Ls, betas, seed=5, n_sweeps=10000, n_metro=1, n_or=10, exchange_ev
     n_ex = n_sweeps // exchange_every if exchange_every else 0
     result = {"L": list(Ls), "betas": [float(x) for x in betas], "n_sweeps": n_sweeps,
               "site_updates_per_s": n_sweeps * (n_metro + n_or) * sites / secs,
-              "tiling": [sim.get_tiling(l) for l in range(len(Ls))], "per_L": {}}
+              "tiling": [sim.get_tiling(l) for l in range(len(Ls))],
+              "tiling_fused": [sim.get_tiling_fused(l) for l in range(len(Ls))], "per_L": {}}
     for li, L in enumerate(Ls):
         N = L ** 3
         rows = []
