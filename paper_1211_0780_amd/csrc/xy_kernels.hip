@@ -500,7 +500,9 @@ void k_tile_f32(SweepArgs a)
                     v.u1 = unit24f(w1[s]);
                     const f2 so = sincos_turns(cur[s]);
                     const f2 sn = sincos_turns(v.prop);
-                    const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
+                    // the multiply-add written out: every instantiation (and the
+                    // queueing path's recomputation) forms the same dE
+                    const float dE = __builtin_fmaf(so.c - sn.c, hx, (so.s - sn.s) * hy);
                     v.pa = __builtin_amdgcn_exp2f(dE * nbl2e);
                     return v;
                 };
@@ -589,7 +591,9 @@ void k_tile_f32(SweepArgs a)
                                            : u0;
                     const f2 so = sincos_turns(cur[s]);
                     const f2 sn = sincos_turns(prop);
-                    const float dE = (so.c - sn.c) * hx + (so.s - sn.s) * hy;
+                    // the multiply-add written out: every instantiation (and the
+                    // queueing path's recomputation) forms the same dE
+                    const float dE = __builtin_fmaf(so.c - sn.c, hx, (so.s - sn.s) * hy);
                     const float pa = __builtin_amdgcn_exp2f(dE * nbl2e);
                     const bool acc = u1 < pa;
                     if (a.recheck && __builtin_fabsf(u1 - pa) < band) {
