@@ -51,9 +51,13 @@ def test_graph_run_equals_eager(gpu, prec):
 
 
 def test_results_independent_of_tiling_and_persistence(gpu):
+    """Tile shapes and workgroup caps (fewer workgroups than items, each
+    taking several in turn) give the same configurations, Metropolis and
+    fused over-relaxation."""
     betas = [0.43, 0.45, 0.47]
     ref = None
-    for ty, tz, grid in [(24, 24, 0), (4, 6, 0), (2, 3, 0), (8, 8, 5), (6, 2, 7), (24, 1, 3)]:
+    for ty, tz, grid in [(24, 24, 0), (4, 6, 0), (2, 3, 0), (8, 8, 5), (6, 2, 7), (24, 1, 3), (24, 24, 15),
+                         (24, 24, 3)]:
         s = make(24, betas, 8)
         set_tiling(s, 0, ty, tz, grid)
         for _ in range(3):
