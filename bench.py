@@ -84,7 +84,8 @@ def cpu_baseline(window=0.0):
     """The oracle on the host: all available cores on one sweep of L = 160
     configurations (one process per configuration), then single-core runs of
     the two small workloads (the L = 8 single-lattice chain in full, and 100
-    sweeps of the L = 32 tempering ladder)."""
+    sweeps of the L = 32 tempering ladder); the single-core list ends with
+    the L = 160 sweep time of the median process of the first leg."""
     import numpy as np
     import oracle
     oracle.build()
@@ -121,6 +122,13 @@ def cpu_baseline(window=0.0):
         pool.join()
     single_core = [{"workload": name, "site_updates": u, "seconds": round(t, 2),
                     "ns_per_update": round(1e9 * t / u, 1)} for (name, _), (u, t) in zip(singles, sres)]
+    # the L = 160 sweep of one process of the all-cores leg (median process;
+    # every core busy meanwhile, so memory bandwidth is shared)
+    per_proc = sorted(r[1] for r in res)[len(res) // 2]
+    single_core.append({"workload": f"L={L} single configuration, one sweep of {N_METRO} + {N_OR} "
+                                    "(median process of the all-cores leg, every core busy)",
+                        "site_updates": res[0][0], "seconds": round(per_proc, 2),
+                        "ns_per_update": round(1e9 * per_proc / res[0][0], 1)})
     return {
         "value": updates / busy,
         "unit": "site-updates/s",
