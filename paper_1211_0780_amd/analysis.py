@@ -14,6 +14,9 @@ Sec. III (Binder cumulant and stiffness crossings, bootstrap resampling):
   crossing        beta where two curves (e.g. U_L or rho_s L for two sizes)
                   cross, by linear interpolation of their difference, with a
                   bootstrap error over the per-beta error bars
+  combine_runs    mean of one estimate over independent runs (different
+                  seeds) with a standard error from their spread, and how
+                  that spread compares with the per-run error bars
   swap_rates      acceptance of each neighbouring pair from exchange counters
 
 The finite-size-scaling fits of Sec. III (data collapse, exponents) need the
@@ -103,6 +106,26 @@ def crossing(betas, ya, ea, yb, eb, n_boot=2000, seed=0):
             samples.append(c)
     err = float(np.std(samples, ddof=1)) if len(samples) > 1 else float("nan")
     return float(b0), err
+
+
+def combine_runs(values, errors):
+    """Mean over independent runs of an estimate (one per seed), its standard
+    error from the spread of the runs, which assumes nothing about the
+    per-run error bars (autocorrelation, correlated ladder points), and the
+    ratio of that spread to the mean per-run error (about 1 when the per-run
+    errors are right).  Returns (mean, standard error, ratio); runs whose
+    value is nan (no crossing) are left out, and fewer than two give nan
+    for the error and the ratio."""
+    v = np.asarray(values, dtype=np.float64)
+    e = np.asarray(errors, dtype=np.float64)
+    keep = ~np.isnan(v)
+    v, e = v[keep], e[keep]
+    if v.size == 0:
+        return float("nan"), float("nan"), float("nan")
+    if v.size < 2:
+        return float(v[0]), float("nan"), float("nan")
+    sd = float(np.std(v, ddof=1))
+    return float(v.mean()), sd / np.sqrt(v.size), sd / float(np.mean(e))
 
 
 def swap_rates(n_acc, n_exchange_steps, tau0=0):

@@ -8,7 +8,14 @@ reports per L and beta: e, U_L (Eq. (5)), Q_2 (Eq. (11)), rho_s L (Eqs. (6),
 successive sizes (Sec. III: both cross at T_c).  It is a miniature of the
 paper's analysis for small L, not a reproduction of its exponents.
 
+With --seeds K the batch is run K times from independent seeds and each
+crossing is also reported as the mean over the runs with a standard error
+from their spread: the per-run bootstrap errors treat the ladder points as
+independent and the bins as uncorrelated, which for the Binder crossings
+understates the run-to-run spread.
+
     python -m paper_1211_0780_amd.fss --L 8 16 --sweeps 4000
+    python -m paper_1211_0780_amd.fss --sweeps 10000 --seeds 5
 """
 import argparse
 import json
@@ -80,11 +87,34 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=10000)
     ap.add_argument("--n-or", type=int, default=10)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--seeds", type=int, default=1,
+                    help="independent runs from seeds seed, seed + 1, ...; crossings combined over them")
     args = ap.parse_args(argv)
     betas = np.linspace(args.beta[0], args.beta[1], args.replicas)
-    res = run_batch(args.L, betas, seed=args.seed, n_sweeps=args.sweeps, n_or=args.n_or)
+    if args.seeds <= 1:
+        res = run_batch(args.L, betas, seed=args.seed, n_sweeps=args.sweeps, n_or=args.n_or)
+    else:
+        runs = [run_batch(args.L, betas, seed=args.seed + i, n_sweeps=args.sweeps, n_or=args.n_or)
+                for i in range(args.seeds)]
+        res = {"seeds": [args.seed + i for i in range(args.seeds)], "runs": runs,
+               "combined": combine_crossings(runs)}
     json.dump(res, sys.stdout)
     print()
+
+
+def combine_crossings(runs):
+    """Each crossing of run_batch results from independent seeds, combined:
+    mean, standard error from the spread over the runs, and the ratio of that
+    spread to the mean per-run bootstrap error."""
+    out = []
+    for i, c0 in enumerate(runs[0]["crossings"]):
+        vals = [r["crossings"][i]["beta_cross"] for r in runs]
+        errs = [r["crossings"][i]["err"] for r in runs]
+        m, se, ratio = A.combine_runs(vals, errs)
+        out.append({"pair": c0["pair"], "quantity": c0["quantity"], "beta_cross": m, "err": se,
+                    "spread_over_quoted": ratio, "n_runs": len(runs),
+                    "per_run": [[v, e] for v, e in zip(vals, errs)]})
+    return out
 
 
 if __name__ == "__main__":

@@ -56,6 +56,22 @@ def test_crossing_of_two_lines():
     assert np.isnan(A.crossing(betas, ya, e, ya + 1, e)[0])
 
 
+def test_combine_runs_of_known_spread():
+    # 400 runs of an estimate 0.4542 + N(0, 2e-4) whose per-run error bars
+    # claim 1e-4: the spread is twice the claim
+    rng = np.random.default_rng(11)
+    v = 0.4542 + 2e-4 * rng.standard_normal(400)
+    m, se, ratio = A.combine_runs(v, np.full(400, 1e-4))
+    assert m == pytest.approx(0.4542, abs=4 * 2e-4 / 20)
+    assert se == pytest.approx(2e-4 / 20, rel=0.1)
+    assert ratio == pytest.approx(2.0, rel=0.1)
+    # exact small case and the nan handling
+    m, se, ratio = A.combine_runs([1.0, 3.0, np.nan], [1.0, 1.0, 5.0])
+    assert (m, se, ratio) == pytest.approx((2.0, 1.0, np.sqrt(2.0)))
+    m, se, ratio = A.combine_runs([1.0], [0.5])
+    assert m == 1.0 and np.isnan(se) and np.isnan(ratio)
+
+
 def test_swap_rates_parity_bookkeeping():
     # pairs 0, 2 attempted on even tau, 1 on odd tau; 10 exchange steps
     rates = A.swap_rates([5, 2, 5, 0], 10)
@@ -78,3 +94,17 @@ def test_ladder_rejects_bad_input():
         ladder.respace([0.1, 0.1, 0.2], [0.5, 0.5])
     with pytest.raises(ValueError):
         ladder.respace([0.1, 0.2], [0.5, 0.5])
+
+
+def test_fss_combine_crossings_over_seeds():
+    from paper_1211_0780_amd.fss import combine_crossings
+    runs = [{"crossings": [{"pair": [8, 16], "quantity": "U", "beta_cross": b, "err": 1e-4},
+                           {"pair": [8, 16], "quantity": "rhoL", "beta_cross": float("nan"), "err": float("nan")}]}
+            for b in (0.4540, 0.4542, 0.4544)]
+    c = combine_crossings(runs)
+    assert [x["quantity"] for x in c] == ["U", "rhoL"]
+    assert c[0]["beta_cross"] == pytest.approx(0.4542)
+    assert c[0]["err"] == pytest.approx(2e-4 / np.sqrt(3))
+    assert c[0]["spread_over_quoted"] == pytest.approx(2.0)
+    assert c[0]["n_runs"] == 3 and len(c[0]["per_run"]) == 3
+    assert np.isnan(c[1]["beta_cross"])
