@@ -252,6 +252,42 @@ def test_measure_special_states(gpu, prec):
     assert obs[1, 2] == pytest.approx(0.0, abs=tol)
 
 
+@pytest.mark.parametrize("fused", [True, False])
+def test_over_relaxation_special_field_directions(gpu, fused):
+    """Colour 1 uniform at 0, pi/2, pi, pi/4 and 3 pi/4 (one replica each),
+    colour 0 random: every colour-0 site sees a field of length 6 along +x,
+    +y, -x and the two diagonals, where the octant reduction's argument
+    t = (|hy| - |hx|)/(|hy| + |hx|) is -1, +1, -1 and about 0 with either
+    sign of hx*hy (Eq. (2)).  One over-relaxation substep, both colours
+    checked site by site against the oracle: with two fused substeps, the
+    first read from the fused pass's second buffer; with one substep, which
+    runs as two half-sweeps."""
+    from gpu_util import check_or_substep
+    L = 8
+    N = L ** 3
+    dirs = [0.0, np.pi / 2, np.pi, np.pi / 4, 3 * np.pi / 4]
+    s = make(L, list(np.linspace(0.40, 0.50, len(dirs))), 77, "fp32")
+    rng = np.random.default_rng(77)
+    m1 = colour_mask(L, 1)
+    start = []
+    for k, phi in enumerate(dirs):
+        th = rng.uniform(0.0, 2 * np.pi, N)
+        th[m1] = phi
+        s.set_angles(th, 0, k)
+        start.append(s.get_angles(0, k))
+    worst = 0.0
+    if fused:
+        s.sweep(0, 2)
+        for k in range(len(dirs)):
+            mid = s.get_angles_fused_mid(0, k)
+            worst = max(worst, check_or_substep(start[k], mid, L), check_or_substep(mid, s.get_angles(0, k), L))
+    else:
+        s.sweep(0, 1)
+        for k in range(len(dirs)):
+            worst = max(worst, check_or_substep(start[k], s.get_angles(0, k), L))
+    print(f"[over-relaxation, axis and diagonal fields, fused={fused}] largest deviation {worst:.3f} of the bound")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_exchange_matches_oracle(gpu, prec):
     """Eq. (3) decisions and the resulting permutation, over many steps."""
