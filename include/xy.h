@@ -23,6 +23,13 @@
  *
  * Conventions used by every entry point
  * -------------------------------------
+ *  - "Device buffer" below means memory the GPU reaches: device memory of
+ *    the context's GPU, managed memory, or host memory pinned with
+ *    hipHostMalloc (kernels write it through its mapped address).  Pageable
+ *    host memory, memory of another GPU, or a buffer whose allocation ends
+ *    before the bytes a call writes (checked where HIP reports the
+ *    allocation's range) makes the call return XY_ERR_ARG before it enqueues
+ *    anything.
  *  - Lattice l is a periodic L_l x L_l x L_l simple cubic lattice with
  *    N_l = L_l^3 sites, site index i = x + L*(y + L*z).  J = k_B = 1 and
  *    beta = 1/T.
@@ -144,8 +151,9 @@ xy_status xy_sweep(xy_ctx ctx, int32_t n_metro, int32_t n_or);
  * the six neighbour spins (every bond has one end of each colour).  Terms
  * are formed in the configuration's precision and accumulated in float64.
  * obs has 5*R_total doubles; if
- * obs_on_device is nonzero it is a device pointer and the call is
- * asynchronous, otherwise it is host memory and the call waits for it.
+ * obs_on_device is nonzero it is a device buffer (see the conventions:
+ * pinned host memory qualifies) and the call is asynchronous, otherwise it
+ * is any host memory and the call waits for it.
  * Returns XY_ERR_STATE (host destination only) if any energy or
  * magnetisation measured since the sentinel was last reported is not finite,
  * and clears the sentinel.
@@ -170,7 +178,8 @@ xy_status xy_exchange(xy_ctx ctx, int64_t *n_acc);
  * exchange_every is 0 or 1) and replayed: n_sweeps
  * times { xy_sweep(n_metro, n_or); measure into obs_dev; exchange if
  * (sweep index + 1) % exchange_every == 0 }.  exchange_every = 0 disables
- * exchange.  obs_dev: device buffer of n_sweeps*5*R_total doubles, sweep s at
+ * exchange.  obs_dev: device buffer (pinned host memory qualifies) of
+ * n_sweeps*5*R_total doubles, sweep s at
  * offset 5*R_total*s, laid out as xy_measure; may be NULL to skip the copy
  * (observables are still computed for the exchange).  Graphs are cached per
  * (n_metro, n_or, obs_dev, bonds ring); reusing a ring reuses its graphs,
@@ -199,7 +208,7 @@ xy_status xy_sweep_profiled(xy_ctx ctx, int32_t n_metro, int32_t n_or, double *m
 
 /*
  * xy_run that also records, per sweep, the bond sums behind the spin
- * stiffness of Eq. (6) into bonds_dev (device, n_sweeps*6*R_total doubles,
+ * stiffness of Eq. (6) into bonds_dev (device buffer, n_sweeps*6*R_total doubles,
  * sweep s at offset 6*R_total*s, position p at 6*p): {C_x, C_y, C_z, I_x,
  * I_y, I_z} with C_mu = sum_i cos(theta_i - theta_{i+mu}) and
  * I_mu = sum_i sin(theta_i - theta_{i+mu}), each bond (i, i+mu) once, in

@@ -703,6 +703,37 @@ size_t xy_angles_bytes(const xy_config *cfg)
     return (size_t)total_elems(cfg) * (cfg->prec == XY_FP32 ? 4 : 8);
 }
 
+// A caller buffer that kernels (or device-side copies) of this context use:
+// device memory of the context's GPU, managed memory, or host memory pinned
+// with hipHostMalloc, which the GPU reaches through its mapped address.
+// Pageable host memory and memory of another GPU are rejected here rather
+// than faulting inside a kernel, and so is a buffer whose allocation ends
+// before `bytes` where HIP reports the allocation's range (a tensor carved
+// from a larger pool can only be checked against the pool).  *dev receives
+// the address kernels use: p itself (unified addressing gives pinned host
+// memory the same address on the device).
+xy_status gpu_buffer(xy_ctx c, void *p, size_t bytes, const char *what, void **dev)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess || a.devicePointer == nullptr) {
+        (void)hipGetLastError();
+        return fail(c, XY_ERR_ARG, std::string(what) + " is neither device memory nor pinned host memory");
+    }
+    if (a.type == hipMemoryTypeDevice && a.device != c->dev)
+        return fail(c, XY_ERR_ARG, std::string(what) + " is memory of another GPU");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, a.devicePointer) == hipSuccess && base) {
+        if ((char *)a.devicePointer + bytes > (char *)base + size)
+            return fail(c, XY_ERR_ARG, std::string(what) + " is smaller than the " + std::to_string(bytes) +
+                                           " bytes the call writes");
+    } else {
+        (void)hipGetLastError();
+    }
+    *dev = p;
+    return XY_OK;
+}
+
 xy_status xy_init(const xy_config *cfg, xy_ctx *out)
 {
     if (!out) return fail(nullptr, XY_ERR_ARG, "out is NULL");
@@ -762,7 +793,8 @@ xy_status xy_init(const xy_config *cfg, xy_ctx *out)
         return bail(XY_ERR_HIP);
     }
     if (cfg->angles_dev) {
-        c->ang = cfg->angles_dev;
+        if ((st = gpu_buffer(c, cfg->angles_dev, (size_t)c->n_elems * c->elem, "angles_dev", &c->ang)))
+            return bail(st);
         c->own_ang = false;
     } else {
         if ((st = dev_alloc(c, (char **)&c->ang, (size_t)c->n_elems * c->elem))) return bail(st);
@@ -910,9 +942,11 @@ xy_status xy_measure(xy_ctx c, double *obs, int32_t obs_on_device)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
     if (!obs) return fail(c, XY_ERR_ARG, "obs is NULL");
-    xy_status st = enqueue_measure_kernel(c);
-    if (st) return st;
-    double *dst = obs_on_device ? obs : c->d_obs;
+    double *dst = c->d_obs;
+    xy_status st;
+    if (obs_on_device && (st = gpu_buffer(c, obs, sizeof(double) * 5 * c->R_total, "obs", (void **)&dst)))
+        return st;
+    if ((st = enqueue_measure_kernel(c))) return st;
     if ((st = enqueue_finalize(c, kPartMeas, dst, 0, true, false, c->d_bonds))) return st;
     c->e_fresh = true;
     c->bonds_fresh = true;
@@ -966,6 +1000,12 @@ xy_status xy_run_ex(xy_ctx c, int32_t n_sweeps, int32_t n_metro, int32_t n_or, i
     xy_status st0 = poll_bad(c);
     if (st0) return st0;
     if (n_sweeps == 0) return XY_OK;
+    if (obs_dev && (st0 = gpu_buffer(c, obs_dev, sizeof(double) * 5 * c->R_total * (size_t)n_sweeps, "obs_dev",
+                                     (void **)&obs_dev)))
+        return st0;
+    if (bonds_dev && (st0 = gpu_buffer(c, bonds_dev, sizeof(double) * 6 * c->R_total * (size_t)n_sweeps,
+                                       "bonds_dev", (void **)&bonds_dev)))
+        return st0;
 
     // Captured graphs of `batch` sweeps, each sweep + measure (+ exchange),
     // then one counter update (t, tau, observable ring).  Nothing in the
@@ -1279,6 +1319,10 @@ xy_status xy_get_bond_sums(xy_ctx c, double *out, int32_t out_on_device)
 {
     if (!c) return fail(nullptr, XY_ERR_ARG, "ctx is NULL");
     if (!out) return fail(c, XY_ERR_ARG, "out is NULL");
+    if (out_on_device) {
+        xy_status st = gpu_buffer(c, out, sizeof(double) * 6 * c->R_total, "out", (void **)&out);
+        if (st) return st;
+    }
     if (!c->bonds_fresh) {
         xy_status st = enqueue_measure_kernel(c);
         if (!st) st = enqueue_finalize(c, kPartMeas, nullptr, 0, true, false, c->d_bonds);

@@ -92,10 +92,12 @@ class Sim:
         return None
 
     def run(self, n_sweeps, n_metro=1, n_or=1, exchange_every=1, obs=None, bonds=None):
-        """Graph-replayed loop.  ``obs`` (optional) is a float64 CUDA tensor of
+        """Graph-replayed loop.  ``obs`` (optional) is a float64 tensor of
         shape (n_sweeps, R_total, 5) receiving every sweep's observables;
         ``bonds`` (optional) one of shape (n_sweeps, R_total, 6) receiving the
-        bond sums (C_x, C_y, C_z, I_x, I_y, I_z) of Eq. (6)."""
+        bond sums (C_x, C_y, C_z, I_x, I_y, I_z) of Eq. (6).  Either may live
+        on the GPU or in pinned host memory (``pin_memory=True``), which the
+        kernels write directly."""
         self._check_ring("obs", obs, n_sweeps * self.R_total * 5)
         self._check_ring("bonds", bonds, n_sweeps * self.R_total * 6)
         ptr = ctypes.c_void_p(obs.data_ptr()) if obs is not None else None
@@ -108,8 +110,9 @@ class Sim:
         if t is None:
             return
         import torch
-        if t.dtype != torch.float64 or t.device.type != "cuda" or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        reachable = t.device.type == "cuda" or (t.device.type == "cpu" and t.is_pinned())
+        if t.dtype != torch.float64 or not reachable or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU or in pinned host memory")
         if t.numel() < n:
             raise ValueError(f"{name} holds {t.numel()} values, the run writes {n}")
 

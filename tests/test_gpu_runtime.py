@@ -449,3 +449,63 @@ def test_autotuned_schedule_gives_the_same_chain(gpu):
     print(f"[autotune] fused tiles after tuning {tuned}, grid cap {a.get_tiling(0)[2]}")
     a.close()
     b.close()
+
+
+def test_run_rings_in_pinned_host_memory(gpu):
+    """The loop writes its observable and bond rings straight into pinned
+    host memory (the GPU reaches it through its mapped address): the same
+    values as device rings from the same start, and the same chain."""
+    betas = list(np.linspace(0.44, 0.46, 3))
+    a = make(8, betas, 41)
+    b = make(8, betas, 41)
+    n = 6
+    od = torch.zeros((n, 3, 5), dtype=torch.float64, device=gpu)
+    bd = torch.zeros((n, 3, 6), dtype=torch.float64, device=gpu)
+    oh = torch.zeros((n, 3, 5), dtype=torch.float64, pin_memory=True)
+    bh = torch.zeros((n, 3, 6), dtype=torch.float64, pin_memory=True)
+    a.run(n, 1, 2, exchange_every=1, obs=od, bonds=bd)
+    b.run(n, 1, 2, exchange_every=1, obs=oh, bonds=bh)
+    torch.cuda.synchronize()
+    assert np.array_equal(od.cpu().numpy(), oh.numpy())
+    assert np.array_equal(bd.cpu().numpy(), bh.numpy())
+    assert np.array_equal(gpu_states(a), gpu_states(b))
+    assert np.all(oh.numpy()[:, :, 0] < 0)
+
+
+def _allocation_bytes_after(ptr):
+    """Bytes from ptr to the end of its HIP allocation (None if not reported)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    base, size = ctypes.c_void_p(), ctypes.c_size_t()
+    if hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), ctypes.c_void_p(ptr)) != 0:
+        hip.hipGetLastError()
+        return None
+    return base.value + size.value - ptr
+
+
+def test_buffers_the_gpu_cannot_write_are_rejected(gpu):
+    """Pageable host memory where the GPU writes (the loop's rings, xy_measure
+    and xy_get_bond_sums with their on-device flag) and a ring shorter than
+    the run (its allocation ends first) are refused with XY_ERR_ARG before
+    anything is enqueued: the chain and the counters do not move."""
+    import ctypes
+    from paper_1211_0780_amd import _capi as C
+    s = make(8, [0.44, 0.46], 5)
+    before = gpu_states(s)
+    counters = s.counters()
+    host = np.zeros(64 * 2 * 6)
+    p = host.ctypes.data_as(ctypes.c_void_p)
+    assert C.lib().xy_run_ex(s._ctx, 8, 1, 1, 1, p, None) == C.XY_ERR_ARG
+    assert C.lib().xy_run_ex(s._ctx, 8, 1, 1, 1, None, p) == C.XY_ERR_ARG
+    assert C.lib().xy_measure(s._ctx, p, 1) == C.XY_ERR_ARG
+    assert C.lib().xy_get_bond_sums(s._ctx, p, 1) == C.XY_ERR_ARG
+    # a pinned ring whose allocation ends one sweep's records too early
+    ring = torch.zeros(16, dtype=torch.float64, pin_memory=True)
+    room = _allocation_bytes_after(ring.data_ptr())
+    if room is None:
+        pytest.skip("the allocation range of pinned host memory is not reported")
+    n_fit = room // (5 * 2 * 8)
+    assert C.lib().xy_run_ex(s._ctx, int(n_fit + 1), 1, 1, 1, ctypes.c_void_p(ring.data_ptr()), None) == C.XY_ERR_ARG
+    assert "smaller than" in C.lib().xy_last_error(s._ctx).decode()
+    assert s.counters() == counters
+    assert np.array_equal(gpu_states(s), before)

@@ -1,6 +1,7 @@
 """Argument checks of the Python binding that run before anything reaches
-the library (no GPU needed): device rings the kernels write through must be
-contiguous float64 CUDA tensors large enough for the call."""
+the library (no GPU needed): rings the kernels write through must be
+contiguous float64 tensors on the GPU or in pinned host memory, large
+enough for the call."""
 import os
 import sys
 
@@ -13,12 +14,12 @@ from paper_1211_0780_amd.sim import Sim  # noqa: E402
 
 
 @pytest.mark.parametrize("t", [
-    torch.zeros(10, dtype=torch.float64),           # host memory
+    torch.zeros(10, dtype=torch.float64),           # pageable host memory
     torch.zeros(10, dtype=torch.float32),           # wrong dtype
     torch.zeros(10, 2, dtype=torch.float64).t(),    # strided view
 ], ids=["host", "float32", "strided"])
 def test_ring_rejected(t):
-    with pytest.raises(ValueError, match="float64 CUDA tensor"):
+    with pytest.raises(ValueError, match="float64 tensor on the GPU or in pinned host memory"):
         Sim._check_ring(None, "obs", t, 5)
 
 
