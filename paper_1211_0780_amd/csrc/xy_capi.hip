@@ -1330,8 +1330,9 @@ xy_status xy_get_bond_sums(xy_ctx c, double *out, int32_t out_on_device)
         c->e_fresh = true;
         c->bonds_fresh = true;
     }
+    // the runtime tells device memory from pinned host memory (hipMemcpyDefault)
     XY_HIP(c, hipMemcpyAsync(out, c->d_bonds, sizeof(double) * 6 * c->R_total,
-                             out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+                             out_on_device ? hipMemcpyDefault : hipMemcpyDeviceToHost, c->stream));
     if (!out_on_device) XY_HIP(c, hipStreamSynchronize(c->stream));
     return XY_OK;
 }

@@ -470,6 +470,17 @@ def test_run_rings_in_pinned_host_memory(gpu):
     assert np.array_equal(bd.cpu().numpy(), bh.numpy())
     assert np.array_equal(gpu_states(a), gpu_states(b))
     assert np.all(oh.numpy()[:, :, 0] < 0)
+    # xy_measure and xy_get_bond_sums with a pinned host destination and the
+    # on-device flag (asynchronous, written by the device)
+    import ctypes
+    from paper_1211_0780_amd import _capi as C
+    mo = torch.zeros((3, 5), dtype=torch.float64, pin_memory=True)
+    mb = torch.zeros((3, 6), dtype=torch.float64, pin_memory=True)
+    C.check(C.lib().xy_measure(b._ctx, ctypes.c_void_p(mo.data_ptr()), 1), b._ctx)
+    C.check(C.lib().xy_get_bond_sums(b._ctx, ctypes.c_void_p(mb.data_ptr()), 1), b._ctx)
+    torch.cuda.synchronize()
+    assert np.allclose(mo.numpy(), a.measure(), rtol=1e-12, atol=1e-9)
+    assert np.allclose(mb.numpy(), a.bond_sums(), rtol=1e-12, atol=1e-9)
 
 
 def _allocation_bytes_after(ptr):
