@@ -723,8 +723,8 @@ xy_status gpu_buffer(xy_ctx c, void *p, size_t bytes, const char *what, void **d
         return fail(c, XY_ERR_ARG, std::string(what) + " is memory of another GPU");
     hipDeviceptr_t base = nullptr;
     size_t size = 0;
-    if (hipMemGetAddressRange(&base, &size, a.devicePointer) == hipSuccess && base) {
-        if ((char *)a.devicePointer + bytes > (char *)base + size)
+    if (hipMemGetAddressRange(&base, &size, p) == hipSuccess && base) {
+        if ((char *)p + bytes > (char *)base + size)
             return fail(c, XY_ERR_ARG, std::string(what) + " is smaller than the " + std::to_string(bytes) +
                                            " bytes the call writes");
     } else {
