@@ -15,7 +15,10 @@ Prints one JSON line:
             kernel could reach), timed with HIP events on the simulation's
             stream around each group of consecutive launches of one kind
   cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload
-  fp64_plain    the plain FP64 single-replica kernels at L = 160, for reference
+  fp64_plain    the plain FP64 single-replica kernels at L = 160, for reference,
+                and the speed-up of the batch over them
+  repeats   the timed region run twice more after the per-kernel timing, with
+            the median of the three (value stays the first region's rate)
 """
 import argparse
 import hashlib
@@ -260,6 +263,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=2,
+                    help="extra timed regions of --steps sweeps after the first (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5,
                     help="extra eagerly launched sweeps timed per kernel with HIP events")
@@ -348,6 +353,18 @@ def main():
             tot[k] = tot.get(k, 0.0) + ms[k]
             cnt[k] = cnt.get(k, 0) + n[k]
     print(f"[bench] per-kernel timing over {args.profile_steps} sweeps done", file=sys.stderr, flush=True)
+    # further timed regions of the same length (three in all with the first):
+    # their median and spread are reported beside `value`, which stays the
+    # first region's rate
+    rep_ms = []
+    for _ in range(args.repeats):
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        sim.run(args.steps, N_METRO, N_OR, exchange_every=1, obs=obs)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        rep_ms.append(r0.elapsed_time(r1) / args.steps)
+    print(f"[bench] {args.repeats} repeat regions done", file=sys.stderr, flush=True)
     ms_total = ev0.elapsed_time(ev1)
     sec = ms_total / 1e3
     updates = args.steps * (N_METRO + N_OR) * N * R
@@ -489,6 +506,13 @@ def main():
             "hbm_frac_at_24B": round(fp64_rate * BYTES_PER_UPDATE_F64 / 1e9 / HBM_PEAK_GBS, 4),
         },
         "fp32_vs_fp64": fp32_vs_fp64,
+        "repeats": {
+            "ms_per_step": [round(x, 5) for x in [ms_total / args.steps] + rep_ms],
+            "median_ms_per_step": round(float(np.median([ms_total / args.steps] + rep_ms)), 5),
+            "median_value": updates / (float(np.median([ms_total / args.steps] + rep_ms)) * args.steps / 1e3),
+            "note": "the timed region run again right after the per-kernel timing; value is the first",
+        },
+        "speedup_vs_fp64_plain_single_replica": round(value / fp64_rate, 2),
         "metropolis_acceptance": round(acceptance, 5),
         "recheck_overflow": overflow,
         "wall_s_timed": wall,
