@@ -1,6 +1,9 @@
 """Fit the float32 polynomial kernels used by the FP32 HIP path.
 
-  atan(q)/pi  ~ q * A(q^2),   q in [0, 1]            (A: degree NA in q^2)
+  atan(q)/pi  ~ q * A(q^2),   q in [0, 1]            (A: degree NA in q^2;
+                                                      odd, so the same error on
+                                                      [-1, 1], where the kernels
+                                                      evaluate it)
   sin(2 pi r) ~ r * S(r^2),   cos(2 pi r) ~ C(r^2),   r in [-1/8, 1/8] turns
 
 Coefficients come from a weighted least-squares fit on Chebyshev nodes refined
