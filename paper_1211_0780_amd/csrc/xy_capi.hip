@@ -712,7 +712,7 @@ size_t xy_angles_bytes(const xy_config *cfg)
 // from a larger pool can only be checked against the pool).  *dev receives
 // the address kernels use: p itself (unified addressing gives pinned host
 // memory the same address on the device).
-xy_status gpu_buffer(xy_ctx c, void *p, size_t bytes, const char *what, void **dev)
+static xy_status gpu_buffer(xy_ctx c, void *p, size_t bytes, const char *what, void **dev)
 {
     hipPointerAttribute_t a{};
     if (hipPointerGetAttributes(&a, p) != hipSuccess || a.devicePointer == nullptr) {
@@ -1550,7 +1550,7 @@ struct BlobHeader {
 };
 constexpr char kMagic[8] = {'X', 'Y', 'S', 'T', 'A', 'T', 'E', '1'};
 
-size_t blob_size(xy_ctx c)
+static size_t blob_size(xy_ctx c)
 {
     return sizeof(BlobHeader) + sizeof(int32_t) * 2 * c->n_lat + sizeof(double) * c->R_total +
            sizeof(int32_t) * 2 * c->R_total + sizeof(unsigned long long) * 2 * c->R_total +

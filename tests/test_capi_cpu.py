@@ -33,6 +33,21 @@ def test_library_exports_every_declared_symbol(xylib):
     assert set(C.EXPORTS) <= set(declared_functions())
 
 
+def test_library_exports_no_undeclared_c_symbol(xylib):
+    """Every C-linkage function the library exports is declared in the header
+    (internal helpers have internal linkage; C++ symbols are mangled)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", xylib._name], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.split() and ln.split()[1] in "TtWw"}
+    c_funcs = {n for n in exported if not n.startswith("_Z")}
+    assert c_funcs <= set(declared_functions()), sorted(c_funcs - set(declared_functions()))
+
+
 def _cfg(L, R, beta, prec=C.XY_FP32, start=C.XY_START_RANDOM):
     cfg = C.XYConfig()
     Ls = (ctypes.c_int32 * len(L))(*L)
