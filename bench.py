@@ -85,10 +85,11 @@ def cpu_model():
 
 def cpu_baseline(window=0.0):
     """The oracle on the host: all available cores on one sweep of L = 160
-    configurations (one process per configuration), then single-core runs of
-    the two small workloads (the L = 8 single-lattice chain in full, and 100
-    sweeps of the L = 32 tempering ladder); the single-core list ends with
-    the L = 160 sweep time of the median process of the first leg."""
+    configurations (one process per configuration), then single-core runs,
+    side by side, of the L = 8 single-lattice chain in full, 100 sweeps of the
+    L = 32 tempering ladder and one sweep of one L = 160 configuration; the
+    single-core list ends with the L = 160 sweep time of the median process
+    of the first leg."""
     import numpy as np
     import oracle
     oracle.build()
@@ -116,7 +117,9 @@ def cpu_baseline(window=0.0):
     singles = [("L=8 single lattice, beta 0.4542, 1 + 1, 10^4 sweeps, measurement every sweep (in full)",
                 (8, [0.4542], 1, 10000, 1, 1, 0)),
                ("L=32 ladder, 16 replicas over [0.450, 0.458], 1 + 5, exchange every sweep, 100 sweeps",
-                (32, list(np.linspace(0.450, 0.458, 16)), 2, 100, 1, 5, 1))]
+                (32, list(np.linspace(0.450, 0.458, 16)), 2, 100, 1, 5, 1)),
+               (f"L={L} single configuration, beta 0.4542, one sweep of {N_METRO} + {N_OR} with its measurement",
+                (L, [0.4542], SEED, 1, N_METRO, N_OR, 0))]
     pool = mp.get_context("spawn").Pool(len(singles))
     try:
         sres = pool.map(_oracle_run, [a for _, a in singles])
@@ -126,7 +129,8 @@ def cpu_baseline(window=0.0):
     single_core = [{"workload": name, "site_updates": u, "seconds": round(t, 2),
                     "ns_per_update": round(1e9 * t / u, 1)} for (name, _), (u, t) in zip(singles, sres)]
     # the L = 160 sweep of one process of the all-cores leg (median process;
-    # every core busy meanwhile, so memory bandwidth is shared)
+    # every core busy meanwhile, so memory bandwidth is shared), beside the
+    # same sweep alone on one core above
     per_proc = sorted(r[1] for r in res)[len(res) // 2]
     single_core.append({"workload": f"L={L} single configuration, one sweep of {N_METRO} + {N_OR} "
                                     "(median process of the all-cores leg, every core busy)",
