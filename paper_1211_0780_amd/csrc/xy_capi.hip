@@ -216,7 +216,8 @@ Tiling default_tiling(int L, int R)
 // LDS of the fused over-relaxation kernel for a tile of ty rows of L/2
 // sites: two old-colour-1 plane buffers of the kernel's fixed size
 // (spt + 2) * kBlock and three new-colour-0 plane buffers of (ty + 2) * L/2
-// (cos, sin) pairs.  Tiles are limited to five columns per thread, so that
+// (cos, sin) pairs (the measuring variants rotate through three, the plain
+// substep uses two; one size serves both).  Tiles are limited to five columns per thread, so that
 // any batch of admissible tiles fits 64 KiB ((5 * 5 + 7) * kBlock pairs).
 size_t or2_lds_bytes(int ty, int half)
 {
@@ -619,7 +620,8 @@ void build_layout(xy_ctx c)
             p0_elems = std::max(p0_elems, (size_t)(t.TY + 2) * d.half);
         }
         // two old-colour-1 plane buffers at the kernel's fixed size (spt2 + 2) * kBlock,
-        // a bound on (TY + 4) * L/2, then three new-colour-0 plane buffers
+        // a bound on (TY + 4) * L/2, then three new-colour-0 plane buffers (two used
+        // by the plain substep)
         c->lds2 = ((size_t)2 * (c->spt2 + 2) * kBlock + 3 * p0_elems) * 2 * sizeof(float);
         c->items_or2 = item2;
     }

@@ -167,6 +167,9 @@ def test_autotune_leaves_the_chain_untouched(gpu):
     (160, [0.4542], (16, 20)),       # five columns per thread
     (64, [0.44, 0.46], (32, 8)),     # four columns per thread
     (48, [0.45], (48, 6)),           # one tile per slot in y, five columns per thread
+    (160, [0.4542], (8, 40)),        # the benchmark's fused tiles: three columns per thread
+    (96, [0.44, 0.46], (12, 8)),     # three columns, 576 of 768 slots filled
+    (192, [0.45], (8, 8)),           # three columns, all filled
 ])
 def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     """The fused substep performs the same float32 operations in the same
