@@ -10,7 +10,9 @@ Coefficients come from a weighted least-squares fit on Chebyshev nodes refined
 by a few Lawson (iteratively reweighted) passes toward the minimax solution,
 then the float32 Horner evaluation is checked on a dense grid.  Run:
     python fit_polys.py
-and paste the printed constants into xy_device.h.
+and paste the printed constants into xy_device.h (the kernels use the
+degree-13 atan fit, NA = 7, and the degree-7 sine / degree-8 cosine fit
+behind XY_POLY_SINCOS).
 """
 import numpy as np
 
@@ -34,7 +36,7 @@ def horner32(c, s):
     return acc
 
 
-def fit_atan(NA=8):
+def fit_atan(NA=7):
     q = np.cos(np.linspace(0, np.pi, 4000)) * 0.5 + 0.5
     f = np.arctan(q) / np.pi
     basis = lambda x: np.stack([x ** (2 * k + 1) for k in range(NA)], axis=1)

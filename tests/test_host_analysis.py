@@ -56,6 +56,28 @@ def test_crossing_of_two_lines():
     assert np.isnan(A.crossing(betas, ya, e, ya + 1, e)[0])
 
 
+def test_precision_ensemble_binder_jackknife():
+    """The ensemble study's U_L error: with m^2 the same in every ladder U_L
+    is linear in the mean of m^4, and the leave-one-ladder-out jackknife of a
+    linear function of a mean is exactly its standard error; identical
+    ladders give no error and the closed form of Eq. (5)."""
+    from paper_1211_0780_amd import precision as P
+    rng = np.random.default_rng(3)
+    K, R = 9, 4
+    m = np.zeros((K, R, 5))
+    m[:, :, 3] = 0.02
+    m[:, :, 4] = 6e-4 + 1e-5 * rng.standard_normal((K, R))
+    u, err = P._binder_jk(m)
+    assert np.allclose(u, 1.0 - m[:, :, 4].mean(0) / (3 * 0.02 ** 2), rtol=0, atol=1e-15)
+    se = m[:, :, 4].std(0, ddof=1) / np.sqrt(K) / (3 * 0.02 ** 2)
+    assert np.allclose(err, se, rtol=1e-10)
+    same = np.repeat(m[:1], K, axis=0)
+    u1, e1 = P._binder_jk(same)
+    assert np.allclose(u1, 1.0 - same[0, :, 4] / (3 * same[0, :, 3] ** 2)) and np.all(e1 < 1e-15)
+    with pytest.raises(ValueError):
+        P.compare_ladders(8, [0.45, 0.46], n32=1, n64=4)
+
+
 def test_combine_runs_of_known_spread():
     # 400 runs of an estimate 0.4542 + N(0, 2e-4) whose per-run error bars
     # claim 1e-4: the spread is twice the claim
