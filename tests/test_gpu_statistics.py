@@ -110,6 +110,25 @@ def test_fp32_matches_fp64_on_a_ladder(gpu):
         assert row["abs_err_e"] <= 1e-6 and row["abs_err_abs_m"] <= 1e-6
 
 
+def test_fp32_matches_fp64_over_independent_ladders(gpu):
+    """Ensemble form: 32 float32 and 32 float64 ladders (L = 16, 16 replicas
+    over [0.44, 0.47], 1 + 8, exchange every sweep), each an independent
+    chain, with standard errors from the spread of the ladders rather than
+    from binning.  Two families, each at its Bonferroni bound: the four
+    ladder averages (e, |m|, m^2, m^4) and the 80 per-beta differences."""
+    from paper_1211_0780_amd.precision import compare_ladders
+    res = compare_ladders(16, np.linspace(0.44, 0.47, 16), n32=32, n64=32, n_sweeps=2000,
+                          seeds=(21, 1021))
+    zl = np.array([v["z"] for v in res["ladder_average"].values()])
+    gate_l, gate_b = bonferroni_z(zl.size), bonferroni_z(res["n_compared"])
+    print(f"[L=16 fp32 vs fp64, 32 + 32 ladders] ladder averages z = {np.round(zl, 2).tolist()} "
+          f"(gate {gate_l:.2f}); per beta max |z| {res['max_abs_z']:.2f} (gate {gate_b:.2f}), "
+          f"rms {res['rms_z']:.2f}, within 2 sigma {res['frac_within_2sigma']:.3f}")
+    assert np.all(np.abs(zl) <= gate_l)
+    assert res["max_abs_z"] <= gate_b
+    assert 0.5 <= res["rms_z"] <= 2.0
+
+
 def test_fss_batch_binder_crossing(gpu):
     """The batched finite-size-scaling set: L in {24, 32, 48, 64, 96, 128}, 16 replicas each over
     [0.452, 0.456], one launch per half-sweep for the whole batch, graph
