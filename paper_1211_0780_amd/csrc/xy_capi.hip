@@ -217,8 +217,9 @@ Tiling default_tiling(int L, int R)
 // sites: two old-colour-1 plane buffers of the kernel's fixed size
 // (spt + 2) * kBlock and three new-colour-0 plane buffers of (ty + 2) * L/2
 // (cos, sin) pairs (the measuring variants rotate through three, the plain
-// substep uses two; one size serves both).  Tiles are limited to five columns per thread, so that
-// any batch of admissible tiles fits 64 KiB ((5 * 5 + 7) * kBlock pairs).
+// substep uses two; one size serves both).  Tiles are limited to five
+// columns per thread, so that any batch of admissible tiles fits 64 KiB
+// ((5 * 5 + 7) * kBlock pairs).
 size_t or2_lds_bytes(int ty, int half)
 {
     const int spt = spt_for(ty * half);
