@@ -131,6 +131,48 @@ def test_full_size_metropolis_every_site(bench_sim):
     assert s.recheck_overflow() == 0
 
 
+def test_full_size_windowed_metropolis_every_site(gpu):
+    """The restricted-window proposal theta' = theta + 2.0 (U - 1/2) (the
+    second Metropolis workload, timed by bench.py --window 2.0) at full size
+    in the benchmark's tiling: one Metropolis substep, every site of both
+    colours of beta-positions 0 and 31 against the oracle's half-sweeps from
+    the GPU's own states, decisions differing only within 1e-6 of the
+    threshold."""
+    from gpu_util import check_metro_half
+    L, seed, w = L_BENCH, 6, 2.0
+    betas = np.linspace(0.4538, 0.4546, R_BENCH)
+    s = make(L, [betas], seed)
+    s.set_tiling(0, *BENCH_TILING, 0)
+    s.set_tiling_fused(0, *BENCH_TILING_FUSED)
+    s.set_proposal_window(w)
+    s.sweep(1, 2)
+    t = s.counters()[0]
+    ks = (0, R_BENCH - 1)
+    before = {k: s.get_angles(0, k) for k in ks}
+    acc0 = s.metro_accepts()
+    s.sweep(1, 0)
+    acc1 = s.metro_accepts()
+    m0 = colour_mask(L, 0)
+    flips, n_acc = 0, 0
+    for k in ks:
+        after = s.get_angles(0, k)
+        n_ref = 0
+        for c in (0, 1):
+            start = before[k] if c == 0 else np.where(m0, after, before[k])
+            got = np.where(m0, after, before[k]) if c == 0 else after
+            ref = start.copy()
+            n_ref += oracle.metro_half(ref, L, betas[k], seed, t, 0, k, 0, c, window=w)
+            margin = oracle.metro_margin(start, L, betas[k], seed, t, 0, k, 0, c, window=w)
+            flips += check_metro_half(start, got, ref, margin, L, c, 2e-5)
+        assert abs(int(acc1[k] - acc0[k]) - n_ref) <= flips
+        n_acc += n_ref
+    print(f"[full-size windowed metropolis] acceptance {n_acc / (len(ks) * L ** 3):.3f}, "
+          f"{flips} near-threshold flips")
+    assert flips <= 5
+    assert s.recheck_overflow() == 0
+    s.close()
+
+
 def test_full_size_measurement(bench_sim):
     s, betas = bench_sim
     obs = s.measure()
