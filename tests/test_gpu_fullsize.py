@@ -173,6 +173,27 @@ def test_full_size_windowed_metropolis_every_site(gpu):
     s.close()
 
 
+def test_full_size_bond_sums(bench_sim):
+    """The bond sums behind Eq. (6) at full size: one graph-replayed sweep
+    with a bond ring, so the last over-relaxation launch is the fused
+    measuring kernel that also forms the sums, against the standalone bond
+    kernel on the same configurations and against the oracle's sums."""
+    import torch
+    s, betas = bench_sim
+    N = L_BENCH ** 3
+    obs = torch.zeros((1, R_BENCH, 5), dtype=torch.float64, device="cuda")
+    bonds = torch.zeros((1, R_BENCH, 6), dtype=torch.float64, device="cuda")
+    s.run(1, 1, 10, exchange_every=0, obs=obs, bonds=bonds)
+    torch.cuda.synchronize()
+    fused = bonds[0].cpu().numpy()
+    assert np.allclose(fused, s.bond_sums(), rtol=1e-12, atol=1e-6)
+    for k in (0, R_BENCH - 1):
+        ref = oracle.bond_sums(s.get_angles(0, k), L_BENCH)
+        assert np.allclose(fused[k], ref, rtol=0, atol=2e-6 * N), (fused[k], ref)
+    # the energy of the same launch is the negative sum of the C terms
+    assert np.allclose(obs[0, :, 0].cpu().numpy(), -fused[:, :3].sum(axis=1), rtol=0, atol=2e-6 * N)
+
+
 def test_full_size_measurement(bench_sim):
     s, betas = bench_sim
     obs = s.measure()
