@@ -97,6 +97,9 @@ def _or_bound(start, L, prec):
     ("fp32", 16, 3, (4, 2)),     # several y-tiles and z-chunks
     ("fp32", 24, 2, None),       # 288 sites per plane: ragged last wave
     ("fp32", 12, 2, (12, 3)),
+    ("fp32", 4, 3, None),        # the smallest lattice: halo rows and planes wrap onto the tile
+    ("fp64", 4, 2, None),
+    ("fp32", 6, 2, None),        # L/2 = 3 sites per row and colour
 ])
 def test_half_sweep_parity(gpu, prec, L, R, tiling):
     """One Metropolis substep, then one over-relaxation substep, each colour

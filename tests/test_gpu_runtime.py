@@ -170,6 +170,8 @@ def test_autotune_leaves_the_chain_untouched(gpu):
     (160, [0.4542], (8, 40)),        # the benchmark's fused tiles: three columns per thread
     (96, [0.44, 0.46], (12, 8)),     # three columns, 576 of 768 slots filled
     (192, [0.45], (8, 8)),           # three columns, all filled
+    (4, [0.44, 0.46], None),         # the smallest lattice: one 4 x 4 tile per slot
+    (6, [0.45], None),               # L/2 = 3 sites per row and colour
 ])
 def test_fused_over_relaxation_equals_two_half_sweeps(gpu, L, betas, tiles):
     """The fused substep performs the same float32 operations in the same
