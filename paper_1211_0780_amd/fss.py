@@ -94,8 +94,10 @@ def main(argv=None):
     if args.seeds <= 1:
         res = run_batch(args.L, betas, seed=args.seed, n_sweeps=args.sweeps, n_or=args.n_or)
     else:
-        runs = [run_batch(args.L, betas, seed=args.seed + i, n_sweeps=args.sweeps, n_or=args.n_or)
-                for i in range(args.seeds)]
+        runs = []
+        for i in range(args.seeds):
+            runs.append(run_batch(args.L, betas, seed=args.seed + i, n_sweeps=args.sweeps, n_or=args.n_or))
+            print(f"[fss] seed {args.seed + i}: run {i + 1} of {args.seeds} done", file=sys.stderr, flush=True)
         res = {"seeds": [args.seed + i for i in range(args.seeds)], "runs": runs,
                "combined": combine_crossings(runs)}
     json.dump(res, sys.stdout)
