@@ -158,10 +158,15 @@ def proposal_text(window):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources and the compiler flags they are built with
+    (the traffic counters belong to one build of the kernels)."""
+    from paper_1211_0780_amd import build_lib
     h = hashlib.sha256()
-    for f in ("xy_kernels.hip", "xy_device.h", "xy_kernels.h"):
+    for f in ("xy_kernels.hip", "xy_or2.hip", "xy_or2_kernel.h", "xy_kernel_common.h", "xy_device.h",
+              "xy_kernels.h"):
         with open(os.path.join(ROOT, "paper_1211_0780_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(build_lib.flags_signature().encode())
     return h.hexdigest()[:16]
 
 

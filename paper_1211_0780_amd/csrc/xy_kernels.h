@@ -86,6 +86,9 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, bool full, int spt, int 
 // lead: every lattice of the launch fills the first spt - 1 tile columns (TY * L/2 > (spt - 1) * kBlock)
 hipError_t launch_or2_f32(bool fuse_measure, bool lead, int spt, int grid, size_t lds_bytes, const SweepArgs &a,
                           hipStream_t s, int *per_cu = nullptr);
+// the plain (non-measuring) fused substep, built in its own translation unit
+hipError_t launch_or2_plain(bool lead, int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
+                            int *per_cu);
 hipError_t launch_recheck(const SweepArgs &a, hipStream_t s);
 hipError_t launch_plain_f64(int kind, bool fuse_measure, int grid, const SweepArgs &a, hipStream_t s);
 hipError_t launch_init(bool fp32, bool ordered, const LatDev *lats, int n_lat,

@@ -7,6 +7,11 @@
 // x = 2j + p with p = (c + y + z) & 1.  Its six neighbours all have the other
 // colour and sit at index j in rows (y +- 1, z) and (y, z +- 1), and at
 // j and j + (p ? +1 : -1) (mod L/2) in its own row.
+//
+// The fused over-relaxation substep's kernel template is in
+// xy_or2_kernel.h (its plain instantiations are built from xy_or2.hip, the
+// measuring ones here); the device helpers both files use are in
+// xy_kernel_common.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -14,191 +19,10 @@
 
 #include "xy_device.h"
 #include "xy_kernels.h"
+#include "xy_kernel_common.h"
+#include "xy_or2_kernel.h"
 
 namespace xy {
-
-
-// ---------------------------------------------------------------------------
-// Reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Sum the first nq measurement accumulators (kPartials with the bond sums,
-// kPartialsNoBonds without) over the workgroup in a fixed order and store
-// the item's partials.  Ends with a barrier so the scratch can be reused.
-__device__ __forceinline__ void block_store_partials(const double (&v)[kPartials], double *dst, int nq)
-{
-    __shared__ double red[kBlock / 64][kPartials];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < kPartials; ++q) {
-        if (q < nq) {
-            const double t = wave_sum(v[q]);
-            if (lane == 0) red[wv][q] = t;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < nq) {
-        double acc = 0.0;
-        for (int i = 0; i < kBlock / 64; ++i) acc += red[i][threadIdx.x];
-        dst[threadIdx.x] = acc;
-    }
-    __syncthreads();
-}
-
-// Measurement terms of one colour-1 site i with unit vector (c, s), the field
-// h = (hx, hy) of its six colour-0 neighbours (the sum every update kernel
-// forms, in the same order), those neighbours split by direction (+x, -x, +y,
-// -y, +z, -z) and the colour-0 partner site at the same storage index (pc, ps):
-//   S    += S_i . h_i
-//   M    += S_i + S_partner                (each site counted once)
-// and, when the bond sums of Eq. (6) are asked for,
-//   C_mu += S_i . (S_{i+mu} + S_{i-mu})     bonds (i, i+mu) and (i-mu, i)
-//   I_mu += sin(th_i - th_{i+mu}) - sin(th_i - th_{i-mu})
-// Every bond has exactly one colour-1 end, so S counts each bond once and the
-// energy of Eq. (1) is E = -S (= -(C_x + C_y + C_z) up to rounding).  Each
-// site's terms are formed in the precision of its inputs (float32 on the
-// float32 path: a few 1e-7 relative, like the inputs themselves) and
-// accumulated in float64.
-// The fused multiply-adds are written out so that every kernel that inlines
-// this forms bit-identical terms (left to the compiler, contraction of the
-// products may differ between instantiations).
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename T>
-__device__ __forceinline__ void measure_site(double (&acc)[kPartials], bool bonds, T c, T s, T pc, T ps,
-                                             T hx, T hy, const T (&nc)[6], const T (&ns)[6])
-{
-    acc[0] += (double)fma_t(c, hx, s * hy);
-    acc[1] += (double)c + (double)pc;
-    acc[2] += (double)s + (double)ps;
-    if (bonds) {
-#pragma unroll
-        for (int mu = 0; mu < 3; ++mu) {
-            const T cp = nc[2 * mu], sp = ns[2 * mu];
-            const T cm = nc[2 * mu + 1], sm = ns[2 * mu + 1];
-            const T ssum = s * (sp + sm), cdif = c * (sp - sm);
-            acc[3 + mu] += (double)fma_t(c, cp + cm, ssum);
-            acc[6 + mu] += (double)fma_t(s, cp - cm, -cdif);
-        }
-    }
-}
-
-__device__ __forceinline__ void block_add_accepts(unsigned long long n, unsigned long long *dst)
-{
-    __shared__ unsigned long long red[kBlock / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    n = wave_sum_u64(n);
-    if (lane == 0) red[wv] = n;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-        for (int i = 0; i < kBlock / 64; ++i) s += red[i];
-        if (s) atomicAdd(dst, s);
-    }
-    __syncthreads();
-}
-
-// Values that are the same in every lane, moved to scalar registers (loads
-// through kernel-argument pointers otherwise land in vector registers, and
-// buffer descriptors built from them would need per-lane loops).
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t uni64(int64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ LatDev load_lat_uniform(const LatDev *p)
-{
-    LatDev d = *p;
-    d.L = uni(d.L);
-    d.half = uni(d.half);
-    d.R = uni(d.R);
-    d.lat = uni(d.lat);
-    d.base = uni64(d.base);
-    d.N = uni64(d.N);
-    d.pos_base = uni(d.pos_base);
-    d.TY = uni(d.TY);
-    d.TZ = uni(d.TZ);
-    d.ny = uni(d.ny);
-    d.nz = uni(d.nz);
-    d.item_base = uni(d.item_base);
-    d.items_per_slot = uni(d.items_per_slot);
-    return d;
-}
-
-// Workgroup barrier that orders LDS only.  __syncthreads() also fences
-// global memory, which on gfx9 waits for every outstanding global load and
-// store (one shared counter) and would drain the z-plane prefetch at each
-// plane.  The half-sweep kernels exchange data between lanes through LDS
-// only, so an LDS-scoped release/acquire around s_barrier is sufficient.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Workgroups are dealt round-robin to the 8 XCDs (block b runs on XCD b mod 8).
-// Map block ids so that each XCD walks a contiguous range of items: tiles
-// that share halo rows (neighbouring y-tiles of one slot and z-chunk) then run
-// at the same time on the same XCD and meet in its L2.  A bijection on
-// [0, G); with a persistent grid that is a multiple of 8, every id a block
-// visits stays on that block's XCD.
-__device__ __forceinline__ int xcd_item(int b, int G)
-{
-    constexpr int kXcd = 8;
-    const int q = G / kXcd, r = G - q * kXcd;
-    const int x = b % kXcd, i = b / kXcd;
-    return x * q + min(x, r) + i;
-}
-
-__device__ __forceinline__ int find_lattice(const LatDev *lats, int n_lat, int item)
-{
-    int li = 0;
-    while (li + 1 < n_lat && item >= lats[li + 1].item_base) ++li;
-    return li;
-}
-
-// ---------------------------------------------------------------------------
-// Raw buffer access to one colour array of one slot: a scalar base and byte
-// size, a per-lane byte offset (constant over z) and a scalar byte offset
-// for the plane.  Out-of-range accesses read 0 / are dropped by hardware.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t colour_rsrc(const float *base, int64_t n)
-{
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(uint32_t)(n * 4), 0x00020000);
-}
-
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-
-// Stores carry the non-temporal hint (cache-policy bit 1, `nt`): no kernel
-// reads back what it writes in the same launch, and keeping the new angles
-// out of the way in L2 leaves it to the halo rows that neighbouring tiles
-// re-read (A/B on the L = 160 x 32 sweep: 1.5 % less time; the same hint on
-// the loads cost 6 %).
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 2);
-}
 
 // ---------------------------------------------------------------------------
 // Re-take one queued near-threshold Metropolis decision in float64: the
@@ -658,306 +482,6 @@ void k_tile_f32(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Fused over-relaxation substep: colour 0 then colour 1 of one substep in a
-// single streaming pass, reading the old configuration from `ang` and
-// writing the new one to `ang_dst` (ping-pong buffers, so no tile ever reads
-// a value another tile has already replaced).
-//
-// At step z the kernel updates colour 0 at plane z ("a") and colour 1 at
-// plane z-1 ("b"); b needs colour 0 already updated at planes z-2, z-1, z,
-// which a has produced by then, so the pass is the sequential order of the
-// two half-sweeps.  Colour 0 is also updated, redundantly and without being
-// stored, on the halo rows y0-1, y0+TY and the halo planes z0-1, z0+TZ: the
-// same deterministic arithmetic on the same inputs as the tile that owns
-// them, so colour 1 at the tile edge sees exactly the values that tile
-// writes.  That needs the old colour 1 two rows and two planes out.
-//
-// Per thread: SPT tile columns ("T", rows y0..y0+TY-1), one halo column
-// ("H", rows y0-1 or y0+TY) and one outer column ("O", rows y0-2 or
-// y0+TY+1, old colour 1 only); H and O need 2*(L/2) <= kBlock, so L <= 256.
-// LDS: P1 = old colour 1 (cos, sin) of plane z on rows y0-2..y0+TY+1 and
-// P0 = new colour 0 of plane z on rows y0-1..y0+TY, both double-buffered.
-// b reads new colour 0 of plane z-2 only at its own column: the plain
-// substep carries that value over in registers from the previous step's
-// read of plane z-1 (two P0 buffers, alternating with the step parity, whose
-// addresses need no per-step arithmetic: 8 % fewer VALU instructions, 2 %
-// less time); the measuring variants, already at their register cap, read
-// it from a third P0 buffer in rotation.
-// Loads run two planes ahead in alternating register sets, as in
-// k_tile_f32.  MEAS (kOr2Measure, kOr2MeasureBonds) adds the measurement of
-// the new configuration to b (this substep must then be the last of the
-// sweep); kOr2MeasureBonds also forms the bond sums when a.bonds is set.
-//
-// The measuring pass without the bond terms (the production loop's usual
-// case) needs few enough registers that, capped at 128, four wavefronts fit
-// per SIMD as in the substeps that do not measure (three otherwise): the
-// launch drops from 1.31x to about 1.06x a plain fused substep.  The cap is
-// applied only up to three columns per thread, where it costs a few spilled
-// registers outside the inner loop.
-// ---------------------------------------------------------------------------
-enum Or2Measure : int { kOr2Plain = 0, kOr2Measure = 1, kOr2MeasureBonds = 2 };
-
-constexpr int or2_min_waves(int meas, int spt) { return (meas == kOr2Measure && spt <= 3) ? 4 : 1; }
-
-// Elements of one old-colour-1 plane buffer of the fused kernel: a bound on
-// (TY + 4) * L/2 (TY * L/2 <= SPT * kBlock tile sites, L/2 <= kBlock/2).
-template <int SPT>
-constexpr int kOr2P1Elems = SPT * kBlock + 2 * kBlock;
-
-// LEAD: every lattice of the launch fills the tile's first SPT - 1 columns
-// (TY * L/2 > (SPT - 1) * kBlock), so only the last column needs a guard.
-template <int MEAS, int SPT, bool LEAD>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(or2_min_waves(MEAS, SPT))))
-void k_or2_f32(SweepArgs a)
-{
-    constexpr int P1E = kOr2P1Elems<SPT>;
-    constexpr bool P0ROT = MEAS != kOr2Plain;  // three rotating P0 buffers
-    constexpr bool BONDS = MEAS == kOr2MeasureBonds;
-    extern __shared__ f2 lds[];
-    const int tid = threadIdx.x;
-
-    for (int v = blockIdx.x; v < a.total_items; v += gridDim.x) {
-        const int w = xcd_item(v, a.total_items);
-        const int li = uni(find_lattice(a.lats, a.n_lat, w));
-        const LatDev d = load_lat_uniform(a.lats + li);
-        const int L = d.L, half = d.half, TY = d.TY, TZ = d.TZ;
-        const int wl = w - d.item_base;
-        const int slot = wl / d.items_per_slot;
-        const int rem = wl - slot * d.items_per_slot;
-        const int ty = rem % d.ny, tz = rem / d.ny;
-        const int y0 = ty * TY, z0 = tz * TZ;
-        const uint32_t plane_b = (uint32_t)L * (uint32_t)half * 4u;
-        const int64_t nh = d.N / 2;
-        const float *src = (const float *)a.ang + d.base + (int64_t)slot * d.N;
-        float *dst = (float *)a.ang_dst + d.base + (int64_t)slot * d.N;
-        const __amdgpu_buffer_rsrc_t r0s = colour_rsrc(src, nh);
-        const __amdgpu_buffer_rsrc_t r1s = colour_rsrc(src + nh, nh);
-        const __amdgpu_buffer_rsrc_t r0d = colour_rsrc(dst, nh);
-        const __amdgpu_buffer_rsrc_t r1d = colour_rsrc(dst + nh, nh);
-        const __amdgpu_buffer_rsrc_t rnull = colour_rsrc(src, 0);
-        // P1 buffers at compile-time offsets (the alternating steps address
-        // them through immediate LDS offsets); the P0 buffers after them
-        const int rows0 = TY + 2;
-        f2 *P1[2] = {lds, lds + P1E};
-        f2 *P0base = lds + 2 * P1E;
-        auto P0 = [&](int b) { return P0base + b * rows0 * half; };
-        auto wrapy = [L](int y) { return y < 0 ? y + L : (y >= L ? y - L : y); };
-        auto wrapz = wrapy;
-        auto xm = [half](int j) { return j == 0 ? half - 1 : j - 1; };
-        auto xp = [half](int j) { return j + 1 == half ? 0 : j + 1; };
-
-        // ---- slot geometry (constant over z) ----
-        // A tile column's LDS index is its in-plane index plus a uniform
-        // shift (P1 rows start two rows above the tile, P0 rows one), and its
-        // x-neighbour is a fixed delta away on even and on odd steps: for
-        // colour 0 at (y, z) and colour 1 at (y, z-1) alike it is j+1 when
-        // (y + z) is odd, j-1 when even (wrapping within the row).
-        uint32_t voffT[SPT];
-        int dxe[SPT], dxo[SPT];
-        bool okT[SPT], pz0[SPT];
-        const int zs = wrapz(z0 - 1);  // first step's plane
-        const int sh1 = 2 * half - y0 * half, sh0 = half - y0 * half;
-#pragma unroll
-        for (int s = 0; s < SPT; ++s) {
-            const int f = tid + s * kBlock;
-            okT[s] = (LEAD && s < SPT - 1) || f < TY * half;
-            const int fl = okT[s] ? f : 0;
-            const int yl = fl / half, j = fl - yl * half, y = y0 + yl;
-            voffT[s] = (uint32_t)(y * half + j) * 4u;
-            const bool podd = ((y + zs) & 1) != 0;
-            pz0[s] = podd;
-            const int dp = xp(j) - j, dm = xm(j) - j;
-            dxe[s] = podd ? dp : dm;
-            dxo[s] = podd ? dm : dp;
-        }
-        auto l1T = [&](int s) { return (int)(voffT[s] >> 2) + sh1; };
-        auto l0T = [&](int s) { return (int)(voffT[s] >> 2) + sh0; };
-        // halo rows on the last 2 * L/2 threads: the last tile column is
-        // populated from the first thread on, so the halo goes to the
-        // wavefronts that have fewer tile columns
-        const int hbase = kBlock - 2 * half;
-        const bool okH = tid >= hbase;
-        const int eH = okH ? tid - hbase : 0;
-        const int rH = eH >= half, jH = eH - rH * half;
-        const int yH = rH ? wrapy(y0 + TY) : wrapy(y0 - 1);
-        const uint32_t voffH = (uint32_t)(yH * half + jH) * 4u;
-        const int l1H = (rH ? TY + 2 : 1) * half + jH;
-        const int l0H = (rH ? TY + 1 : 0) * half + jH;
-        const bool poddH = ((yH + zs) & 1) != 0;
-        const int l1Hxe = (rH ? TY + 2 : 1) * half + (poddH ? xp(jH) : xm(jH));
-        const int l1Hxo = (rH ? TY + 2 : 1) * half + (poddH ? xm(jH) : xp(jH));
-        const int yO = rH ? wrapy(y0 + TY + 1) : wrapy(y0 - 2);
-        const uint32_t voffO = (uint32_t)(yO * half + jH) * 4u;
-        const int l1O = (rH ? TY + 3 : 0) * half + jH;
-
-        // ---- prologue: state for the first step (plane zs = z0-1) ----
-        auto pb = [&](int z) { return (uint32_t)wrapz(z) * plane_b; };
-        // Old colour 1 of plane z-1 stays in the P1 buffer that is rewritten
-        // only at the end of step z and new colour 0 of plane z-1 (and z-2
-        // with three P0 buffers) in the other P0 buffers, so only plane z+1
-        // (old colour 1), plane z and, with two P0 buffers, plane z-2 at the
-        // tile columns (new colour 0) are held in registers.
-        f2 c1p[SPT], c0z2[SPT];
-        float r1m[SPT], r1c[SPT], r1p[SPT], t0[SPT];
-        float aT1[SPT], aT0[SPT], bT1[SPT], bT0[SPT];
-        f2 hp;
-        float ht0, aH1, aH0, bH1, bH0, aO, bO;
-#pragma unroll
-        for (int s = 0; s < SPT; ++s) {
-            r1m[s] = bload(r1s, voffT[s], pb(z0 - 2));
-            r1c[s] = bload(r1s, voffT[s], pb(z0 - 1));
-            r1p[s] = bload(r1s, voffT[s], pb(z0));
-            t0[s] = bload(r0s, voffT[s], pb(z0 - 1));
-            aT1[s] = bload(r1s, voffT[s], pb(z0 + 1));
-            aT0[s] = bload(r0s, voffT[s], pb(z0));
-            P1[1][l1T(s)] = sincos_turns(r1m[s]);
-            P1[0][l1T(s)] = sincos_turns(r1c[s]);
-            c1p[s] = sincos_turns(r1p[s]);
-        }
-        const f2 hm0 = sincos_turns(bload(r1s, voffH, pb(z0 - 2)));
-        const f2 hc0 = sincos_turns(bload(r1s, voffH, pb(z0 - 1)));
-        hp = sincos_turns(bload(r1s, voffH, pb(z0)));
-        ht0 = bload(r0s, voffH, pb(z0 - 1));
-        aH1 = bload(r1s, voffH, pb(z0 + 1));
-        aH0 = bload(r0s, voffH, pb(z0));
-        const f2 o0 = sincos_turns(bload(r1s, voffO, pb(z0 - 1)));
-        aO = bload(r1s, voffO, pb(z0));
-        if (okH) {
-            P1[1][l1H] = hm0;
-            P1[0][l1H] = hc0;
-            P1[0][l1O] = o0;
-        }
-        lds_barrier();
-
-        double acc[kPartials];
-#pragma unroll
-        for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
-
-        // ---- one step: a at plane z = z0-1+zz, b at plane z-1 ----
-        auto step = [&](const int zz, const int par, float (&preT1)[SPT], float (&preT0)[SPT],
-                        float &preH1, float &preH0, float &preO, float (&nxtT1)[SPT],
-                        float (&nxtT0)[SPT], float &nxtH1, float &nxtH0, float &nxtO) {
-            const int z = z0 - 1 + zz;
-            const f2 *p1 = P1[par];
-            f2 *p1n = P1[par ^ 1];           // plane z-1 until rewritten with z+1 at the end
-            const int m3 = P0ROT ? zz % 3 : par;
-            f2 *p0w = P0(m3);                  // new colour 0, plane z
-            const f2 *p0r = P0ROT ? P0(m3 == 0 ? 2 : m3 - 1) : P0(par ^ 1);  // plane z-1
-            const f2 *p0r2 = P0(m3 == 2 ? 0 : m3 + 1);  // plane z-2 (three buffers)
-            {
-                // last planes needed: old colour 1 at z0+TZ+1 (z neighbour of
-                // a at z0+TZ), old colour 0 and the outer rows at z0+TZ; all
-                // are issued at step TZ-1
-                const bool need = zz <= TZ - 1;
-                const __amdgpu_buffer_rsrc_t q1 = need ? r1s : rnull;
-                const __amdgpu_buffer_rsrc_t q2 = q1;
-                const __amdgpu_buffer_rsrc_t q0 = need ? r0s : rnull;
-#pragma unroll
-                for (int s = 0; s < SPT; ++s) {
-                    nxtT1[s] = bload(q1, voffT[s], pb(z + 3));
-                    nxtT0[s] = bload(q0, voffT[s], pb(z + 2));
-                }
-                nxtH1 = bload(q1, voffH, pb(z + 3));
-                nxtH0 = bload(q0, voffH, pb(z + 2));
-                nxtO = bload(q2, voffO, pb(z + 2));
-            }
-            const bool store_a = zz >= 1 && zz <= TZ;
-            const uint32_t sz = pb(z), szm = pb(z - 1);
-            // a: colour 0 at plane z on tile and halo columns
-            // Work on columns past the tile (okT false) or past the halo rows
-            // (okH false) is skipped: with TY * L/2 not a multiple of the
-            // block size whole wavefronts have nothing to do in the last
-            // column, and the branch lets them skip it.
-            f2 c0cur[SPT];
-#pragma unroll
-            for (int s = 0; s < SPT; ++s) {
-                if (!okT[s]) continue;
-                const int lc = l1T(s), lx = lc + (par ? dxo[s] : dxe[s]);
-                const f2 n1 = p1[lc - half], n2 = p1[lc + half], n3 = p1[lc], n4 = p1[lx];
-                const f2 c1m = p1n[lc];
-                const float hx = ((c1m.c + c1p[s].c) + (n1.c + n2.c)) + (n3.c + n4.c);
-                const float hy = ((c1m.s + c1p[s].s) + (n1.s + n2.s)) + (n3.s + n4.s);
-                const float nv = overrelax_turns(t0[s], hx, hy);
-                if (store_a) bstore(nv, r0d, voffT[s], sz);
-                c0cur[s] = sincos_turns(nv);
-                p0w[l0T(s)] = c0cur[s];
-            }
-            if (okH) {
-                const int lx = par ? l1Hxo : l1Hxe;
-                const f2 n1 = p1[l1H - half], n2 = p1[l1H + half], n3 = p1[l1H], n4 = p1[lx];
-                const f2 hm = p1n[l1H];
-                const float hx = ((hm.c + hp.c) + (n1.c + n2.c)) + (n3.c + n4.c);
-                const float hy = ((hm.s + hp.s) + (n1.s + n2.s)) + (n3.s + n4.s);
-                p0w[l0H] = sincos_turns(overrelax_turns(ht0, hx, hy));
-            }
-            // b: colour 1 at plane z-1 on tile columns (from the third step
-            // on); with two P0 buffers the own column's colour 0 of plane z-1
-            // read here is kept for the next step's plane z-2
-            if (zz >= 2) {
-#pragma unroll
-                for (int s = 0; s < SPT; ++s) {
-                    if (!okT[s]) continue;
-                    const int lc = l0T(s), lx = lc + (par ? dxo[s] : dxe[s]);
-                    const f2 m1 = p0r[lc - half], m2 = p0r[lc + half], m3 = p0r[lc], m4 = p0r[lx];
-                    const f2 c0m2 = P0ROT ? p0r2[lc] : c0z2[s];
-                    if constexpr (!P0ROT) c0z2[s] = m3;
-                    const float hx = ((c0m2.c + c0cur[s].c) + (m1.c + m2.c)) + (m3.c + m4.c);
-                    const float hy = ((c0m2.s + c0cur[s].s) + (m1.s + m2.s)) + (m3.s + m4.s);
-                    const float nv = overrelax_turns(r1m[s], hx, hy);
-                    bstore(nv, r1d, voffT[s], szm);
-                    if constexpr (MEAS != kOr2Plain) {
-                        // colour 1 at (y, z-1) has x = 2j + p, p = (y + z) & 1
-                        // (L even keeps the parity through the z wrap); the
-                        // same-j neighbour is +x when p = 0, -x when p = 1
-                        const bool podd = pz0[s] != (par != 0);
-                        const f2 xpv = podd ? m4 : m3, xmv = podd ? m3 : m4;
-                        const f2 sc = sincos_turns(nv);
-                        const float nc[6] = {xpv.c, xmv.c, m2.c, m1.c, c0cur[s].c, c0m2.c};
-                        const float ns[6] = {xpv.s, xmv.s, m2.s, m1.s, c0cur[s].s, c0m2.s};
-                        // m3 is the colour-0 site with the same storage index
-                        measure_site(acc, BONDS && a.bonds != 0, sc.c, sc.s, m3.c, m3.s, hx, hy, nc, ns);
-                    }
-                }
-            } else if (!P0ROT && zz == 1) {
-#pragma unroll
-                for (int s = 0; s < SPT; ++s)
-                    if (okT[s]) c0z2[s] = p0r[l0T(s)];
-            }
-            // next plane of old colour 1 into LDS (over plane z-1, which
-            // every lane must have finished reading) and shift the z windows
-            lds_barrier();
-#pragma unroll
-            for (int s = 0; s < SPT; ++s) {
-                if (!okT[s]) continue;
-                p1n[l1T(s)] = c1p[s];
-                c1p[s] = sincos_turns(preT1[s]);
-                r1m[s] = r1c[s];
-                r1c[s] = r1p[s];
-                r1p[s] = preT1[s];
-                t0[s] = preT0[s];
-            }
-            if (okH) {
-                p1n[l1H] = hp;
-                p1n[l1O] = sincos_turns(preO);
-                hp = sincos_turns(preH1);
-                ht0 = preH0;
-            }
-            lds_barrier();
-        };
-
-        const int steps = TZ + 2;
-        for (int zz = 0; zz < steps; zz += 2) {
-            step(zz, 0, aT1, aT0, aH1, aH0, aO, bT1, bT0, bH1, bH0, bO);
-            if (zz + 1 < steps) step(zz + 1, 1, bT1, bT0, bH1, bH0, bO, aT1, aT0, aH1, aH0, aO);
-        }
-        if constexpr (MEAS != kOr2Plain)
-            block_store_partials(acc, a.partials + kPartials * (int64_t)w,
-                                 (BONDS && a.bonds) ? kPartials : kPartialsNoBonds);
-    }
-}
-
-
-// ---------------------------------------------------------------------------
 // Plain FP64 half-sweep: one thread per site of the updated colour, all six
 // neighbours read straight from global memory, every transcendental in
 // double.  A work item is (lattice, slot, block of kBlock sites).
@@ -1206,16 +730,6 @@ __global__ void k_tick(Ctl *ctl, uint32_t dt, uint32_t dtau, uint32_t dring, int
 // workgroups of the selected kernel fit on one CU at the given LDS size (the
 // resident capacity that persistent launches are sized to).
 // ---------------------------------------------------------------------------
-typedef void (*SweepKernel)(SweepArgs);
-
-static hipError_t launch_or_query(SweepKernel k, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
-                                  int *per_cu)
-{
-    if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kBlock, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), lds, s, a);
-    return hipGetLastError();
-}
-
 template <int KIND, bool MEAS, int HALO, bool FULL>
 static hipError_t launch_tile_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
                                   int *per_cu)
@@ -1256,34 +770,10 @@ hipError_t launch_tile_f32(int kind, bool fuse_measure, bool full, int spt, int 
     return hipErrorInvalidValue;
 }
 
-template <int MEAS, bool LEAD>
-static hipError_t launch_or2_spt(int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
-                                 int *per_cu)
-{
-    switch (spt) {
-    case 1: return launch_or_query(k_or2_f32<MEAS, 1, LEAD>, grid, lds, a, s, per_cu);
-    case 2: return launch_or_query(k_or2_f32<MEAS, 2, LEAD>, grid, lds, a, s, per_cu);
-    case 3: return launch_or_query(k_or2_f32<MEAS, 3, LEAD>, grid, lds, a, s, per_cu);
-    case 4: return launch_or_query(k_or2_f32<MEAS, 4, LEAD>, grid, lds, a, s, per_cu);
-    case 5: return launch_or_query(k_or2_f32<MEAS, 5, LEAD>, grid, lds, a, s, per_cu);
-    case 6: return launch_or_query(k_or2_f32<MEAS, 6, LEAD>, grid, lds, a, s, per_cu);
-    case 8: return launch_or_query(k_or2_f32<MEAS, 8, LEAD>, grid, lds, a, s, per_cu);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int MEAS>
-static hipError_t launch_or2_lead(bool lead, int spt, int grid, size_t lds, const SweepArgs &a, hipStream_t s,
-                                  int *per_cu)
-{
-    return lead ? launch_or2_spt<MEAS, true>(spt, grid, lds, a, s, per_cu)
-                : launch_or2_spt<MEAS, false>(spt, grid, lds, a, s, per_cu);
-}
-
 hipError_t launch_or2_f32(bool fuse_measure, bool lead, int spt, int grid, size_t lds, const SweepArgs &a,
                           hipStream_t s, int *per_cu)
 {
-    if (!fuse_measure) return launch_or2_lead<kOr2Plain>(lead, spt, grid, lds, a, s, per_cu);
+    if (!fuse_measure) return launch_or2_plain(lead, spt, grid, lds, a, s, per_cu);
     return a.bonds ? launch_or2_lead<kOr2MeasureBonds>(lead, spt, grid, lds, a, s, per_cu)
                    : launch_or2_lead<kOr2Measure>(lead, spt, grid, lds, a, s, per_cu);
 }
